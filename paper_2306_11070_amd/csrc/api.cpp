@@ -1,0 +1,376 @@
+// C ABI of the codec: argument checks, context workspaces, launch shapes.
+// Every call validates before it launches and returns a huff_status.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+
+#include "common.h"
+
+using namespace huff;
+
+struct huff_ctx {
+    int device = 0;
+    int num_cus = 256;
+    huff_params params{};
+    HistState* hist_st = nullptr;
+    EncState* enc_st = nullptr;
+    unsigned long long* lb = nullptr;
+    uint64_t lb_cap = 0;
+    int32_t* status = nullptr;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+inline bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+inline uint32_t log2u(uint64_t x) { return 63 - __builtin_clzll(x); }
+inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+huff_status hip_status(hipError_t e) { return e == hipSuccess ? HUFF_OK : HUFF_E_HIP; }
+
+huff_params defaults(int num_cus) {
+    huff_params p;
+    p.enc_tile_rounds = 4;
+    p.hist_blocks = (uint32_t)num_cus * 2;
+    p.hist_depth = 32;
+    p.dec_block = 256;
+    return p;
+}
+
+huff_status check_params(const huff_params& p) {
+    if (p.enc_tile_rounds && p.enc_tile_rounds != 1 && p.enc_tile_rounds != 2 && p.enc_tile_rounds != 4 &&
+        p.enc_tile_rounds != 8)
+        return HUFF_E_INVAL;
+    if (p.hist_depth && (!is_pow2(p.hist_depth) || p.hist_depth > (uint32_t)kHistMaxDepth)) return HUFF_E_INVAL;
+    if (p.dec_block && (p.dec_block < 64 || p.dec_block > 256 || p.dec_block % 64)) return HUFF_E_INVAL;
+    return HUFF_OK;
+}
+
+void merge_params(huff_params& dst, const huff_params& src) {
+    if (src.enc_tile_rounds) dst.enc_tile_rounds = src.enc_tile_rounds;
+    if (src.hist_blocks) dst.hist_blocks = src.hist_blocks;
+    if (src.hist_depth) dst.hist_depth = src.hist_depth;
+    if (src.dec_block) dst.dec_block = src.dec_block;
+}
+
+// Grows the look-back array to hold `tiles` entries.  Waits for the device
+// first: kernels queued earlier may still use the old array.
+huff_status ensure_lb(huff_ctx* ctx, uint64_t tiles) {
+    if (tiles <= ctx->lb_cap) return HUFF_OK;
+    uint64_t cap = std::max<uint64_t>(tiles, 1024);
+    cap = std::max(cap, ctx->lb_cap * 2);
+    if (hipDeviceSynchronize() != hipSuccess) return HUFF_E_HIP;
+    if (ctx->lb) (void)hipFree(ctx->lb);
+    ctx->lb = nullptr;
+    ctx->lb_cap = 0;
+    if (hipMalloc(&ctx->lb, cap * sizeof(unsigned long long)) != hipSuccess) return HUFF_E_NOMEM;
+    if (hipMemset(ctx->lb, 0, cap * sizeof(unsigned long long)) != hipSuccess) return HUFF_E_HIP;
+    if (hipDeviceSynchronize() != hipSuccess) return HUFF_E_HIP;
+    ctx->lb_cap = cap;
+    return HUFF_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* huff_strerror(huff_status s) {
+    switch (s) {
+        case HUFF_OK: return "ok";
+        case HUFF_E_INVAL: return "invalid argument";
+        case HUFF_E_CAPACITY: return "output buffer too small";
+        case HUFF_E_CORRUPT: return "corrupt stream";
+        case HUFF_E_NOMEM: return "out of device memory / over budget";
+        case HUFF_E_AGAIN: return "pending";
+        case HUFF_E_HIP: return "HIP runtime error";
+        case HUFF_E_CODELEN: return "code longer than 63 bits";
+        case HUFF_E_NOTFOUND: return "unknown ticket or handle";
+        default: return "unknown status";
+    }
+}
+
+huff_status huff_ctx_create(int device, const huff_params* params, huff_ctx** out) {
+    if (!out) return HUFF_E_INVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return HUFF_E_INVAL;
+    DeviceGuard g(device);
+    huff_ctx* c = new (std::nothrow) huff_ctx();
+    if (!c) return HUFF_E_NOMEM;
+    c->device = device;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
+        c->num_cus = prop.multiProcessorCount;
+    c->params = defaults(c->num_cus);
+    if (params) {
+        if (check_params(*params) != HUFF_OK) { delete c; return HUFF_E_INVAL; }
+        merge_params(c->params, *params);
+    }
+    bool ok = hipMalloc(&c->hist_st, sizeof(HistState)) == hipSuccess &&
+              hipMalloc(&c->enc_st, sizeof(EncState)) == hipSuccess &&
+              hipMalloc(&c->status, 256) == hipSuccess;
+    if (ok) ok = hipMemset(c->hist_st, 0, sizeof(HistState)) == hipSuccess &&
+                 hipMemset(c->enc_st, 0, sizeof(EncState)) == hipSuccess &&
+                 hipMemset(c->status, 0, 256) == hipSuccess;
+    if (ok) {
+        EncState init{0, 0, 1, 0};
+        ok = hipMemcpy(c->enc_st, &init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess;
+    }
+    if (ok) ok = hipDeviceSynchronize() == hipSuccess;
+    if (!ok) { huff_ctx_destroy(c); return HUFF_E_NOMEM; }
+    *out = c;
+    return HUFF_OK;
+}
+
+void huff_ctx_destroy(huff_ctx* c) {
+    if (!c) return;
+    DeviceGuard g(c->device);
+    (void)hipDeviceSynchronize();
+    if (c->hist_st) (void)hipFree(c->hist_st);
+    if (c->enc_st) (void)hipFree(c->enc_st);
+    if (c->lb) (void)hipFree(c->lb);
+    if (c->status) (void)hipFree(c->status);
+    delete c;
+}
+
+huff_status huff_ctx_set_params(huff_ctx* c, const huff_params* p) {
+    if (!c || !p || check_params(*p) != HUFF_OK) return HUFF_E_INVAL;
+    merge_params(c->params, *p);
+    return HUFF_OK;
+}
+
+huff_status huff_ctx_get_params(const huff_ctx* c, huff_params* out) {
+    if (!c || !out) return HUFF_E_INVAL;
+    *out = c->params;
+    return HUFF_OK;
+}
+
+huff_status huff_ctx_status(huff_ctx* c, int32_t* out, int reset) {
+    if (!c || !out) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    if (hipDeviceSynchronize() != hipSuccess) return HUFF_E_HIP;
+    if (hipMemcpy(out, c->status, sizeof(int32_t), hipMemcpyDeviceToHost) != hipSuccess) return HUFF_E_HIP;
+    if (reset && hipMemset(c->status, 0, sizeof(int32_t)) != hipSuccess) return HUFF_E_HIP;
+    if (reset && hipDeviceSynchronize() != hipSuccess) return HUFF_E_HIP;
+    return HUFF_OK;
+}
+
+huff_status huff_histogram(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint64_t* d_hist, void* stream) {
+    if (!c || !d_hist || (n && !d_in) || n >= kMaxN) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = as_stream(stream);
+    if (n == 0) return hip_status(launch_fill_u64(reinterpret_cast<unsigned long long*>(d_hist), 256, 0, s));
+    uint64_t blocks = std::min<uint64_t>(c->params.hist_blocks, (n + 65535) / 65536);
+    blocks = std::max<uint64_t>(blocks, (n >> 31) + 1);  // < 2^31 bytes per workgroup: u32 LDS counters
+    const uint64_t nvec = (n + 15) / 16;
+    const uint64_t per_vec = (nvec + blocks - 1) / blocks;
+    blocks = (nvec + per_vec - 1) / per_vec;
+    HistArgs a;
+    a.in = d_in;
+    a.n = n;
+    a.out = d_hist;
+    a.st = c->hist_st;
+    a.depth_log2 = log2u(c->params.hist_depth);
+    a.per_block = per_vec * 16;
+    return hip_status(launch_histogram(a, (uint32_t)blocks, s));
+}
+
+// ---- host codebook: tie-ruled Huffman lengths, then canonical codes -------
+huff_status huff_build_codebook(const uint64_t hist[256], huff_codebook* out) {
+    if (!hist || !out) return HUFF_E_INVAL;
+    memset(out, 0, sizeof(*out));
+    // present bytes in (count, value) order
+    uint16_t order[256];
+    int k = 0;
+    for (int v = 0; v < 256; ++v)
+        if (hist[v]) order[k++] = (uint16_t)v;
+    std::stable_sort(order, order + k, [&](uint16_t a, uint16_t b) { return hist[a] < hist[b]; });
+    if (k == 1) out->len[order[0]] = 1;
+    if (k >= 2) {
+        // node ids: leaves 0..k-1 in that order, internal nodes k.. in creation order
+        uint64_t w[511];
+        uint16_t parent[511];
+        for (int i = 0; i < k; ++i) w[i] = hist[order[i]];
+        int leaf = 0, inner = k, made = k;
+        auto take = [&]() -> int {
+            const bool use_leaf = leaf < k && (inner == made || w[leaf] <= w[inner]);
+            return use_leaf ? leaf++ : inner++;
+        };
+        for (int m = 0; m < k - 1; ++m) {
+            const int a = take();
+            const int b = take();
+            w[made] = w[a] + w[b];
+            parent[a] = parent[b] = (uint16_t)made;
+            ++made;
+        }
+        uint16_t depth[511];
+        const int root = made - 1;
+        depth[root] = 0;
+        for (int id = root - 1; id >= 0; --id) depth[id] = depth[parent[id]] + 1;
+        for (int i = 0; i < k; ++i) {
+            if (depth[i] > HUFF_MAX_CODE_LEN) { memset(out, 0, sizeof(*out)); return HUFF_E_CODELEN; }
+            out->len[order[i]] = (uint8_t)depth[i];
+        }
+    }
+    // canonical codes: per length, consecutive values in byte order
+    uint32_t count[HUFF_MAX_CODE_LEN + 1] = {0};
+    for (int v = 0; v < 256; ++v)
+        if (out->len[v]) count[out->len[v]]++;
+    uint64_t next[HUFF_MAX_CODE_LEN + 2] = {0};
+    uint64_t code = 0;
+    for (int l = 1; l <= HUFF_MAX_CODE_LEN; ++l) {
+        code = (code + count[l - 1]) << 1;
+        next[l] = code;
+    }
+    for (int v = 0; v < 256; ++v) {
+        const uint8_t l = out->len[v];
+        if (!l) continue;
+        out->code[v] = next[l]++;
+        out->nsym++;
+        out->max_len = std::max<uint32_t>(out->max_len, l);
+    }
+    return HUFF_OK;
+}
+
+uint64_t huff_encoded_bits(const uint64_t hist[256], const huff_codebook* cb) {
+    if (!hist || !cb) return 0;
+    uint64_t t = 0;
+    for (int v = 0; v < 256; ++v) t += hist[v] * cb->len[v];
+    return t;
+}
+
+huff_status huff_build_codebook_device(huff_ctx* c, const uint64_t* d_hist, huff_dcb* d_cb, int32_t* d_status,
+                                       void* stream) {
+    if (!c || !d_hist || !d_cb) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    CbArgs a;
+    memset(&a, 0, sizeof(a));
+    a.hist = d_hist;
+    a.out = d_cb;
+    a.err = d_status ? d_status : c->status;
+    a.from_lengths = 0;
+    return hip_status(launch_codebook(a, as_stream(stream)));
+}
+
+huff_status huff_codebook_upload(huff_ctx* c, const huff_codebook* cb, huff_dcb* d_cb, void* stream) {
+    if (!c || !cb || !d_cb) return HUFF_E_INVAL;
+    // lengths must describe a prefix code: Kraft sum <= 1, exactly
+    unsigned __int128 kraft = 0;
+    const unsigned __int128 one = (unsigned __int128)1 << HUFF_MAX_CODE_LEN;
+    for (int v = 0; v < 256; ++v) {
+        if (cb->len[v] > HUFF_MAX_CODE_LEN) return HUFF_E_CODELEN;
+        if (cb->len[v]) kraft += one >> cb->len[v];
+    }
+    if (kraft > one) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    CbArgs a;
+    memset(&a, 0, sizeof(a));
+    a.out = d_cb;
+    a.err = c->status;
+    a.from_lengths = 1;
+    memcpy(a.len, cb->len, 256);
+    return hip_status(launch_codebook(a, as_stream(stream)));
+}
+
+huff_status huff_encode(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff_dcb* d_cb, uint32_t chunk_size,
+                        uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off, uint32_t sub_size,
+                        uint32_t* d_sub_lo, int32_t* d_status, void* stream) {
+    if (!c || !d_cb || !d_chunk_off || n >= kMaxN) return HUFF_E_INVAL;
+    if (!is_pow2(chunk_size) || chunk_size < 1024 || chunk_size > (64u << 20)) return HUFF_E_INVAL;
+    if (sub_size && (!is_pow2(sub_size) || sub_size < 16 || sub_size > chunk_size || !d_sub_lo)) return HUFF_E_INVAL;
+    if (n && (!d_in || !d_words)) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = as_stream(stream);
+    if (n == 0) return hip_status(launch_encode_empty(d_chunk_off, sub_size ? d_sub_lo : nullptr, s));
+    const uint32_t rounds = c->params.enc_tile_rounds;
+    const uint64_t tile = (uint64_t)rounds * kRoundBytes;
+    const uint64_t ntiles = (n + tile - 1) / tile;
+    huff_status st = ensure_lb(c, ntiles);
+    if (st != HUFF_OK) return st;
+    EncArgs a;
+    memset(&a, 0, sizeof(a));
+    a.files = nullptr;
+    a.one.in = d_in;
+    a.one.n = n;
+    a.one.cb = d_cb;
+    a.one.words = d_words;
+    a.one.nwords = cap_words;
+    a.one.chunk_off = d_chunk_off;
+    a.one.sub_lo = sub_size ? d_sub_lo : nullptr;
+    a.one.status = d_status;
+    a.one.first = 0;
+    a.nfiles = 1;
+    a.chunk_log2 = log2u(chunk_size);
+    a.sub_log2 = sub_size ? log2u(sub_size) : kNoSub;
+    a.rounds = rounds;
+    a.ntiles = ntiles;
+    a.st = c->enc_st;
+    a.lb = c->lb;
+    a.lb_cap = c->lb_cap;
+    a.err = c->status;
+    const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)c->num_cus * 4);
+    return hip_status(launch_encode(a, (uint32_t)grid, s));
+}
+
+huff_status huff_decode(huff_ctx* c, const uint32_t* d_words, uint64_t nwords, const uint64_t* d_chunk_off,
+                        uint64_t n, uint32_t chunk_size, const uint32_t* d_sub_lo, uint32_t sub_size,
+                        const huff_dcb* d_cb, uint8_t* d_out, int32_t* d_status, void* stream) {
+    if (!c || !d_cb || !d_chunk_off || n >= kMaxN) return HUFF_E_INVAL;
+    if (!is_pow2(chunk_size) || chunk_size < 1024 || chunk_size > (64u << 20)) return HUFF_E_INVAL;
+    if (sub_size && (!is_pow2(sub_size) || sub_size < 16 || sub_size > chunk_size || !d_sub_lo)) return HUFF_E_INVAL;
+    if (n == 0) return HUFF_OK;
+    if (!d_out || !d_words || ((uintptr_t)d_words & 15u)) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    const uint32_t item = sub_size ? sub_size : chunk_size;
+    DecArgs a;
+    memset(&a, 0, sizeof(a));
+    a.files = nullptr;
+    a.one.n = n;
+    a.one.cb = d_cb;
+    a.one.words = const_cast<uint32_t*>(d_words);
+    a.one.nwords = nwords;
+    a.one.chunk_off = const_cast<uint64_t*>(d_chunk_off);
+    a.one.sub_lo = const_cast<uint32_t*>(d_sub_lo);
+    a.one.out = d_out;
+    a.one.status = d_status;
+    a.one.first = 0;
+    a.nfiles = 1;
+    a.chunk_log2 = log2u(chunk_size);
+    a.item_log2 = log2u(item);
+    a.use_sub = sub_size ? 1 : 0;
+    a.nitems = (n + item - 1) / item;
+    a.err = c->status;
+    return hip_status(launch_decode(a, c->params.dec_block, as_stream(stream)));
+}
+
+huff_status huff_copy(huff_ctx* c, const void* d_src, void* d_dst, uint64_t bytes, void* stream) {
+    if (!c || (bytes && (!d_src || !d_dst))) return HUFF_E_INVAL;
+    if (bytes == 0) return HUFF_OK;
+    if (((uintptr_t)d_src & 15u) || ((uintptr_t)d_dst & 15u)) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    return hip_status(launch_copy(d_src, d_dst, bytes, as_stream(stream)));
+}
+
+}  // extern "C"
+
+extern "C" uint64_t huff_abi_sizeof(int which) {
+    switch (which) {
+        case 0: return sizeof(huff_dcb);
+        case 1: return sizeof(huff_codebook);
+        case 2: return sizeof(huff_params);
+        default: return 0;
+    }
+}

@@ -1,0 +1,111 @@
+// Internal declarations shared by the HIP kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "huff.h"
+
+namespace huff {
+
+constexpr int kEncThreads = 256;                 // encode workgroup
+constexpr int kUnitBytes = 16;                   // bytes per thread per encode round
+constexpr int kRoundBytes = kEncThreads * kUnitBytes;  // 4 KiB
+constexpr int kCbThreads = 256;                  // codebook workgroup (one per file)
+constexpr int kHistThreads = 512;
+constexpr int kHistMaxDepth = 32;
+constexpr uint32_t kNoSub = 0xFFFFFFFFu;         // sub_log2 when there is no sub index
+constexpr uint64_t kMaxN = 1ull << 38;
+
+// Look-back status word: [63:62] flag, [61:44] epoch, [43:0] bit count.
+constexpr int kEpochBits = 18;
+constexpr uint32_t kEpochMax = (1u << kEpochBits) - 1;
+constexpr uint64_t kValueMask = (1ull << 44) - 1;
+constexpr uint64_t kFlagAgg = 1ull << 62;
+constexpr uint64_t kFlagPre = 2ull << 62;
+
+// Self-resetting encode workspace (device).  ticket/done return to 0 and
+// epoch advances at the end of every launch; status[] entries are tagged
+// with the epoch that wrote them, so no clearing pass is needed.
+struct EncState {
+    uint32_t ticket;
+    uint32_t done;
+    uint32_t epoch;  // 1..kEpochMax
+    uint32_t pad;
+};
+
+// Self-resetting histogram accumulator (device).
+struct HistState {
+    unsigned long long acc[256];
+    uint32_t done;
+    uint32_t pad[63];
+};
+
+// One stream / file as the kernels see it.  Single calls pass one by value;
+// batched calls pass a device table sorted by the first-work-item fields.
+struct FileDesc {
+    const uint8_t* in;        // encode input / decode: unused
+    uint64_t n;               // bytes
+    const huff_dcb* cb;       // codebook read by encode / decode
+    uint32_t* words;          // encode output / decode input
+    uint64_t nwords;          // encode: capacity; decode: valid words
+    uint64_t* chunk_off;      // nchunks + 1
+    uint32_t* sub_lo;         // nsub + 1 or null
+    uint8_t* out;             // decode output
+    int32_t* status;          // per-file status word (may be null)
+    uint64_t first;           // first global work item (tile / sub-block) of this file
+};
+
+struct EncArgs {
+    const FileDesc* files;  // null: single file in `one`
+    FileDesc one;
+    uint32_t nfiles;
+    uint32_t chunk_log2;
+    uint32_t sub_log2;      // kNoSub if no sub index
+    uint32_t rounds;        // 4 KiB rounds per tile
+    uint64_t ntiles;        // total over all files
+    EncState* st;
+    unsigned long long* lb; // look-back status words, >= ntiles
+    uint64_t lb_cap;
+    int32_t* err;           // fallback status word
+};
+
+struct DecArgs {
+    const FileDesc* files;
+    FileDesc one;
+    uint32_t nfiles;
+    uint32_t chunk_log2;
+    uint32_t item_log2;     // log2 of bytes per decode lane (sub_size or chunk_size)
+    uint32_t use_sub;       // 1: start bits from sub_lo, else from chunk_off
+    uint64_t nitems;        // total lanes over all files (files padded to whole blocks)
+    int32_t* err;
+};
+
+struct HistArgs {
+    const uint8_t* in;
+    uint64_t n;
+    uint64_t* out;
+    HistState* st;
+    uint32_t depth_log2;
+    uint64_t per_block;     // bytes per workgroup (multiple of 16)
+};
+
+struct CbArgs {
+    const uint64_t* hist;   // from-histogram mode (null in from-lengths mode)
+    huff_dcb* out;
+    int32_t* err;
+    uint32_t from_lengths;
+    uint8_t len[256];
+};
+
+// Launchers (kernels.hip).  Return hipSuccess or the launch error.
+hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s);
+hipError_t launch_codebook(const CbArgs& a, hipStream_t s);
+hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo, hipStream_t s);
+hipError_t launch_decode(const DecArgs& a, uint32_t block, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
+
+}  // namespace huff

@@ -1,0 +1,388 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle,
+bit for bit, on seeded inputs.  Sizes span several tiles with ragged tails;
+the full-size workloads are checked on sampled chunks and on properties that
+hold at any size."""
+import sys
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    import paper_2306_11070_amd as P
+    P.load()
+    return P
+
+
+@pytest.fixture(scope="module")
+def codec(P):
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = P.Codec(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def dev(a: np.ndarray):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def host_u32(t, n=None):
+    a = t.detach().cpu().numpy().view(np.uint32)
+    return a if n is None else a[:n]
+
+
+def host_u64(t):
+    return t.detach().cpu().numpy().view(np.uint64)
+
+
+def _fib_bytes(k=34, seed=0):
+    fib = [1, 1]
+    while len(fib) < k:
+        fib.append(fib[-1] + fib[-2])
+    a = np.repeat(np.arange(k, dtype=np.uint8), fib[:k])
+    np.random.default_rng(seed).shuffle(a)
+    return a
+
+
+def _data(kind, n, seed=0):
+    if kind == "zipf96":
+        return datagen.zipf_iid(n, 11 + seed, 1.1)
+    if kind == "markov":
+        return datagen.markov(n, 12 + seed)
+    if kind == "zipf256":
+        return datagen.zipf_iid(n, 13 + seed, 0.8, datagen.A256)
+    if kind == "uniform":
+        return np.random.default_rng(seed).integers(0, 256, size=n, dtype=np.uint8)
+    if kind == "const":
+        return np.full(n, 0x41, dtype=np.uint8)
+    if kind == "two":
+        return np.random.default_rng(seed).choice(np.array([3, 250], np.uint8), size=n, p=[0.9, 0.1])
+    raise KeyError(kind)
+
+
+def _check_status(st):
+    torch.cuda.synchronize()
+    v = int(st.item())
+    assert v == 0, f"device status {v}"
+
+
+# ---------------------------------------------------------------- histogram
+@pytest.mark.parametrize("n", [0, 1, 15, 16, 17, 4095, 65543, 1 << 20, (3 << 20) + 5])
+@pytest.mark.parametrize("offset", [0, 3])
+def test_histogram(codec, n, offset):
+    _say(f"histogram n={n} offset={offset}")
+    a = _data("zipf96", n + offset)
+    x = dev(a)[offset:]
+    h = codec.histogram(x)
+    assert np.array_equal(host_u64(h), oracle.histogram(a[offset:]))
+
+
+@pytest.mark.parametrize("depth", [1, 4, 32])
+@pytest.mark.parametrize("kind", ["const", "uniform", "zipf96"])
+def test_histogram_depths(P, kind, depth):
+    _say(f"histogram depth={depth} kind={kind}")
+    c = P.Codec(0, dict(hist_depth=depth, hist_blocks=37))
+    a = _data(kind, 777_777)
+    for _ in range(3):  # the accumulator resets itself between launches
+        h = c.histogram(dev(a))
+        assert np.array_equal(host_u64(h), oracle.histogram(a))
+    c.close()
+
+
+# ----------------------------------------------------------------- codebook
+def _codebook_cases():
+    rng = np.random.default_rng(3)
+    out = []
+    for i in range(40):
+        k = int(rng.integers(1, 257))
+        h = np.zeros(256, dtype=np.uint64)
+        h[rng.choice(256, size=k, replace=False)] = rng.integers(1, [3, 40, 1 << 40][i % 3], size=k, dtype=np.uint64)
+        out.append(h)
+    fib = [1, 1]
+    while len(fib) < 40:
+        fib.append(fib[-1] + fib[-2])
+    h = np.zeros(256, dtype=np.uint64)
+    h[100:140] = fib
+    out.append(h)
+    h = np.zeros(256, dtype=np.uint64)
+    h[:] = 5
+    out.append(h)  # all 256 equal: 8-bit codes
+    h = np.zeros(256, dtype=np.uint64)
+    h[77] = 9
+    out.append(h)  # one symbol
+    out.append(np.zeros(256, dtype=np.uint64))  # empty
+    return out
+
+
+def _lut_expect(ln, code, lut_bits):
+    exp = np.zeros(1 << 12, dtype=np.uint16)
+    for p in range(1 << lut_bits):
+        for v in range(256):
+            l = int(ln[v])
+            if l and l <= lut_bits and (p >> (lut_bits - l)) == int(code[v]):
+                exp[p] = v | (l << 8)
+    return exp
+
+
+@pytest.mark.parametrize("case", range(44))
+def test_codebook_device(P, codec, case):
+    h = _codebook_cases()[case]
+    _say(f"codebook case={case} K={int(np.count_nonzero(h))}")
+    st = codec.new_status()
+    dcb = codec.build_codebook_device(dev(h.view(np.int64)), status=st)
+    _check_status(st)
+    d = P.dcb_to_host(dcb)
+    ln = oracle.code_lengths(h)
+    code = oracle.canonical_codes(ln)
+    assert np.array_equal(np.frombuffer(bytes(d.len), np.uint8), ln)
+    assert np.array_equal(np.ctypeslib.as_array(d.code).astype(np.uint64), code)
+    assert d.nsym == int(np.count_nonzero(ln)) and d.max_len == int(ln.max())
+    assert d.total_bits == oracle.total_bits(h, ln) and d.n == int(h.sum())
+    assert d.lut_bits == min(int(ln.max()), 12)
+    keyed = sorted((int(ln[v]), v) for v in range(256) if ln[v])
+    assert list(np.frombuffer(bytes(d.sorted_sym), np.uint8)[: len(keyed)]) == [v for _, v in keyed]
+    assert np.array_equal(np.ctypeslib.as_array(d.lut), _lut_expect(ln, code, d.lut_bits))
+
+
+def test_codebook_upload(P, codec):
+    _say("codebook upload")
+    a = _data("markov", 300_000)
+    h = oracle.histogram(a)
+    cb = P.build_codebook(h)
+    dcb = codec.codebook_upload(cb)
+    d = P.dcb_to_host(dcb)
+    ln = oracle.code_lengths(h)
+    assert np.array_equal(np.frombuffer(bytes(d.len), np.uint8), ln)
+    assert np.array_equal(np.ctypeslib.as_array(d.code).astype(np.uint64), oracle.canonical_codes(ln))
+    words, off, sub = codec.encode(dev(a), dcb, 4096, 256)
+    r = oracle.compress(a, 4096, sub=256)
+    torch.cuda.synchronize()
+    assert np.array_equal(host_u32(words, r["words"].size), r["words"])
+    assert np.array_equal(host_u64(off), r["chunk_off"])
+
+
+# ------------------------------------------------------------ encode/decode
+ENC_CASES = [
+    ("zipf96", 1 << 20, 65536, 0),
+    ("zipf96", 1 << 20, 65536, 1024),
+    ("markov", 3 * 16384 + 1234, 1024, 16),
+    ("markov", 200_001, 4096, 256),
+    ("zipf256", 500_000, 1 << 20, 4096),
+    ("uniform", 123_457, 2048, 64),
+    ("const", 70_001, 1024, 512),
+    ("two", 99_999, 8192, 128),
+    ("zipf96", 1, 1024, 16),
+    ("zipf96", 15, 1024, 0),
+    ("markov", 4096, 4096, 4096),
+    ("markov", 16384 * 5, 1024, 1024),
+]
+
+
+def _roundtrip(codec, a, chunk, sub):
+    st = codec.new_status()
+    x = dev(a)
+    c = codec.compress(x, chunk, sub, status=st)
+    _check_status(st)
+    r = oracle.compress(a, chunk, sub=sub if sub else None)
+    nw = r["words"].size
+    assert np.array_equal(host_u64(c["hist"]), r["hist"])
+    assert np.array_equal(host_u32(c["words"], nw), r["words"])
+    assert np.array_equal(host_u64(c["chunk_off"]), r["chunk_off"])
+    if sub:
+        assert np.array_equal(host_u32(c["sub_lo"]), r["sub_lo"])
+    out = codec.decompress(c, status=st)
+    _check_status(st)
+    assert torch.equal(out, x)
+    if sub:
+        # the same stream decodes with the chunk index alone
+        out2 = codec.decode(c["words"], c["words"].numel(), c["chunk_off"], a.size, chunk, c["dcb"], status=st)
+        _check_status(st)
+        assert torch.equal(out2, x)
+    return c, r
+
+
+@pytest.mark.parametrize("kind,n,chunk,sub", ENC_CASES)
+def test_encode_decode_parity(codec, kind, n, chunk, sub):
+    _say(f"encode/decode kind={kind} n={n} chunk={chunk} sub={sub}")
+    _roundtrip(codec, _data(kind, n), chunk, sub)
+
+
+@pytest.mark.parametrize("rounds", [1, 2, 4, 8])
+@pytest.mark.parametrize("dec_block", [64, 256])
+def test_launch_shapes_same_output(P, rounds, dec_block):
+    _say(f"launch shapes rounds={rounds} dec_block={dec_block}")
+    c = P.Codec(0, dict(enc_tile_rounds=rounds, dec_block=dec_block))
+    _roundtrip(c, _data("markov", 333_333, seed=rounds), 2048, 64)
+    c.close()
+
+
+def test_unaligned_input(codec):
+    _say("unaligned input")
+    a = _data("zipf96", 100_003)
+    x = dev(np.concatenate([np.zeros(5, np.uint8), a]))[5:]
+    st = codec.new_status()
+    c = codec.compress(x, 1024, 128, status=st)
+    _check_status(st)
+    r = oracle.compress(a, 1024, sub=128)
+    assert np.array_equal(host_u32(c["words"], r["words"].size), r["words"])
+    assert np.array_equal(host_u64(c["chunk_off"]), r["chunk_off"])
+    out = codec.decompress(c, status=st)
+    _check_status(st)
+    assert np.array_equal(out.cpu().numpy(), a)
+
+
+def test_many_launches_reuse_workspace(codec):
+    """The encode workspace resets itself: many calls of varying size in a row."""
+    _say("many launches")
+    rng = np.random.default_rng(5)
+    for i in range(40):
+        n = int(rng.integers(1, 300_000))
+        a = _data("markov" if i % 2 else "zipf256", n, seed=i)
+        c = codec.compress(dev(a), 1024, 64)
+        r = oracle.compress(a, 1024)
+        torch.cuda.synchronize()
+        assert np.array_equal(host_u32(c["words"], r["words"].size), r["words"]), i
+        assert np.array_equal(host_u64(c["chunk_off"]), r["chunk_off"]), i
+    assert codec.status() == 0
+
+
+def test_empty_input(codec):
+    _say("empty input")
+    x = torch.empty(0, dtype=torch.uint8, device="cuda")
+    c = codec.compress(x, 1024, 64)
+    torch.cuda.synchronize()
+    assert host_u64(c["chunk_off"]).tolist() == [0]
+    assert host_u32(c["sub_lo"]).tolist() == [0]
+    assert codec.decompress(c).numel() == 0
+
+
+def test_long_codes_33_bits(codec, P):
+    """Fibonacci counts force a 33-bit code: the generic encode and decode paths."""
+    _say("long codes (33 bits)")
+    a = _fib_bytes(34)
+    _roundtrip(codec, a, 1 << 20, 4096)
+
+
+def test_capacity_error_writes_nothing_beyond(codec):
+    _say("capacity error")
+    a = _data("zipf96", 50_000)
+    x = dev(a)
+    hist = codec.histogram(x)
+    dcb = codec.build_codebook_device(hist)
+    r = oracle.compress(a, 1024)
+    cap = r["words"].size // 2
+    words = torch.full((r["words"].size + 64,), -1, dtype=torch.int32, device="cuda")
+    st = codec.new_status()
+    codec.encode(x, dcb, 1024, 0, words=words[:cap], status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -2
+    assert np.all(host_u32(words)[cap:] == 0xFFFFFFFF)
+    assert np.array_equal(host_u32(words, cap), r["words"][:cap])
+
+
+def test_decode_detects_corruption(codec):
+    _say("corruption")
+    a = _data("markov", 100_000)
+    st = codec.new_status()
+    c = codec.compress(dev(a), 1024, 0, status=st)
+    _check_status(st)
+    bad = c["chunk_off"].clone()
+    bad[5] += 3
+    codec.decode(c["words"], c["words"].numel(), bad, a.size, 1024, c["dcb"], status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -3
+    # one-symbol code: only 0 bits are valid
+    st.zero_()
+    x = dev(np.full(64, 9, np.uint8))
+    c = codec.compress(x, 1024, 0, status=st)
+    _check_status(st)
+    words = torch.full((8,), -1, dtype=torch.int32, device="cuda")
+    codec.decode(words, 8, c["chunk_off"], 64, 1024, c["dcb"], status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -3
+
+
+def test_missing_symbol_reported(codec, P):
+    _say("missing symbol")
+    a = _data("zipf96", 10_000)
+    h = oracle.histogram(a[:5000])
+    if np.count_nonzero(oracle.histogram(a[5000:])[h == 0]) == 0:
+        a[9999] = 0xFF
+    cb = P.build_codebook(h)
+    dcb = codec.codebook_upload(cb)
+    st = codec.new_status()
+    codec.encode(dev(a), dcb, 1024, 0, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == -1
+
+
+# ------------------------------------------------------------ full workloads
+def test_paper_scale_markov_45MiB(codec):
+    """The 45 MiB order-2 Markov text, 256 KiB chunks: full bit-exact parity."""
+    _say("markov 45 MiB")
+    a = datagen.workload("markov_45MiB")
+    _roundtrip(codec, a, 256 << 10, 1024)
+
+
+def test_small_zipf_1MiB(codec):
+    _say("zipf 1 MiB")
+    a = datagen.workload("zipf96_1MiB")
+    _roundtrip(codec, a, 64 << 10, 0)
+
+
+def _bits_of(words: np.ndarray, lo: int, hi: int) -> np.ndarray:
+    """Stream bits [lo, hi) as a 0/1 array (MSB-first words)."""
+    w0, w1 = lo // 32, (hi + 31) // 32
+    b = np.unpackbits(words[w0:w1].astype(">u4").view(np.uint8))
+    return b[lo - 32 * w0: hi - 32 * w0]
+
+
+@pytest.mark.parametrize("name", ["markov_2GiB", "zipf256_2GiB"])
+def test_full_size_2GiB_properties_and_samples(codec, name):
+    """2 GiB streams: exact histogram, T = sum h*len, monotone index ending at
+    T, sampled chunks re-encoded by the oracle, and an exact round trip."""
+    _say(f"{name}: generate")
+    n = 1 << 31
+    chunk = 1 << 20
+    a = datagen.workload(name)
+    x = dev(a)
+    st = codec.new_status()
+    _say(f"{name}: compress")
+    c = codec.compress(x, chunk, 4096, status=st)
+    _check_status(st)
+    h = host_u64(c["hist"])
+    assert np.array_equal(h, np.bincount(a, minlength=256).astype(np.uint64))
+    ln = oracle.code_lengths(h)
+    code = oracle.canonical_codes(ln)
+    T = oracle.total_bits(h, ln)
+    off = host_u64(c["chunk_off"])
+    assert off[0] == 0 and off[-1] == T and np.all(np.diff(off.astype(np.int64)) >= 0)
+    nw = (T + 31) // 32
+    words = host_u32(c["words"], nw)
+    rng = np.random.default_rng(0)
+    for ch in sorted(set(rng.integers(0, n // chunk, size=6).tolist()) | {0, n // chunk - 1}):
+        seg = a[ch * chunk:(ch + 1) * chunk]
+        w, o = oracle.encode(seg, ln, code, chunk)
+        assert int(o[-1]) == int(off[ch + 1] - off[ch])
+        want = _bits_of(w, 0, int(o[-1]))
+        got = _bits_of(words, int(off[ch]), int(off[ch + 1]))
+        assert np.array_equal(got, want), ch
+    _say(f"{name}: decode")
+    out = codec.decompress(c, status=st)
+    _check_status(st)
+    assert torch.equal(out, x)
+    del out, x, c
+    torch.cuda.empty_cache()
