@@ -70,7 +70,7 @@ enum {
 };
 
 #define HUFF_MAX_CODE_LEN 63
-#define HUFF_LUT_BITS 12
+#define HUFF_LUT_BITS 10
 
 /* Host-side canonical codebook (plain data). */
 typedef struct huff_codebook {
@@ -88,7 +88,7 @@ typedef struct huff_codebook {
 typedef struct huff_dcb {
     uint32_t nsym;                /* K */
     uint32_t max_len;             /* longest code length */
-    uint32_t lut_bits;            /* index width of lut[] (min(max_len, 12)) */
+    uint32_t lut_bits;            /* index width of lut[] (min(max_len, HUFF_LUT_BITS)) */
     int32_t status;               /* HUFF_OK or HUFF_E_CODELEN */
     uint64_t total_bits;          /* T = sum h[v]*len[v] (0 if built from lengths) */
     uint64_t n;                   /* sum h[v] (0 if built from lengths) */
@@ -104,10 +104,10 @@ typedef struct huff_dcb {
 
 /* Launch knobs; 0 selects the built-in or autotuned default. */
 typedef struct huff_params {
-    uint32_t enc_tile_rounds; /* encode tile = 4 KiB x rounds (1, 2, 4 or 8) */
     uint32_t hist_blocks;     /* histogram workgroups (persistent grid) */
     uint32_t hist_depth;      /* histogram replicas per workgroup (1..32, power of 2) */
-    uint32_t dec_block;       /* decode workgroup size (64, 128, 192 or 256) */
+    uint32_t dec_block;       /* direct-decode workgroup size (64, 128, 192 or 256) */
+    uint32_t reserved;        /* must be 0 */
 } huff_params;
 
 typedef struct huff_ctx huff_ctx;
@@ -172,6 +172,16 @@ huff_status huff_codebook_upload(huff_ctx* ctx, const huff_codebook* cb, huff_dc
 huff_status huff_encode(huff_ctx* ctx, const uint8_t* d_in, uint64_t n, const huff_dcb* d_cb, uint32_t chunk_size,
                         uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off, uint32_t sub_size,
                         uint32_t* d_sub_lo, int32_t* d_status, void* stream);
+
+/*
+ * The whole compress path in one call, with no host round trip: histogram
+ * of d_in, codebook built on the device into d_cb (and, if d_hist is not
+ * NULL, the histogram copied to d_hist), then huff_encode.  Same arguments
+ * and outputs as huff_histogram + huff_build_codebook_device + huff_encode.
+ */
+huff_status huff_compress(huff_ctx* ctx, const uint8_t* d_in, uint64_t n, uint32_t chunk_size, huff_dcb* d_cb,
+                          uint64_t* d_hist, uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off,
+                          uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, void* stream);
 
 /*
  * Chunk-indexed decode (the inverse of huff_encode): writes n bytes to

@@ -170,12 +170,33 @@ class Codec:
         _check(lib().huff_copy(self._ctx, _ptr(src), _ptr(dst), nbytes, self._stream(stream)), "huff_copy")
 
     # -- whole path conveniences (still only library calls) -------------------
-    def compress(self, x, chunk_size: int, sub_size: int = 0, status=None, stream=None) -> dict:
-        hist = self.histogram(x, stream=stream)
-        dcb = self.build_codebook_device(hist, status=status, stream=stream)
-        words, off, sub = self.encode(x, dcb, chunk_size, sub_size, status=status, stream=stream)
-        return dict(hist=hist, dcb=dcb, words=words, chunk_off=off, sub_lo=sub, n=x.numel(), chunk_size=chunk_size,
-                    sub_size=sub_size)
+    def compress(self, x, chunk_size: int, sub_size: int = 0, status=None, stream=None, out: dict | None = None) -> dict:
+        """huff_compress: histogram, device codebook and encode in one call.
+        `out` may hold preallocated hist/dcb/words/chunk_off/sub_lo tensors."""
+        torch = _torch()
+        x = self._u8(x)
+        n = x.numel()
+        o = dict(out or {})
+        hist = o.get("hist")
+        if hist is None:
+            hist = torch.empty(256, dtype=torch.int64, device=self.device)
+        dcb = o.get("dcb")
+        if dcb is None:
+            dcb = torch.empty(DCB_BYTES, dtype=torch.uint8, device=self.device)
+        words = o.get("words")
+        if words is None:
+            words = torch.empty((n + 3) // 4 + 4, dtype=torch.int32, device=self.device)
+        off = o.get("chunk_off")
+        if off is None:
+            off = torch.empty((n + chunk_size - 1) // chunk_size + 1, dtype=torch.int64, device=self.device)
+        sub = o.get("sub_lo")
+        if sub_size and sub is None:
+            sub = torch.empty((n + sub_size - 1) // sub_size + 1, dtype=torch.int32, device=self.device)
+        _check(lib().huff_compress(self._ctx, _ptr(x), n, chunk_size, _ptr(dcb), _ptr(hist), _ptr(words), words.numel(),
+                                   _ptr(off), sub_size, _ptr(sub) if sub_size else None, _ptr(status),
+                                   self._stream(stream)), "huff_compress")
+        return dict(hist=hist, dcb=dcb, words=words, chunk_off=off, sub_lo=sub if sub_size else None, n=n,
+                    chunk_size=chunk_size, sub_size=sub_size)
 
     def decompress(self, c: dict, out=None, status=None, stream=None):
         return self.decode(c["words"], c["words"].numel(), c["chunk_off"], c["n"], c["chunk_size"], c["dcb"],

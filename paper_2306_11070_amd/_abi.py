@@ -29,12 +29,12 @@ class HuffDcb(ctypes.Structure):
                 ("status", ctypes.c_int32), ("total_bits", ctypes.c_uint64), ("n", ctypes.c_uint64),
                 ("len", ctypes.c_uint8 * 256), ("sorted_sym", ctypes.c_uint8 * 256), ("code", ctypes.c_uint64 * 256),
                 ("first_code", ctypes.c_uint64 * 64), ("first_index", ctypes.c_uint32 * 64),
-                ("count", ctypes.c_uint32 * 64), ("enc", ctypes.c_uint32 * 256), ("lut", ctypes.c_uint16 * 4096)]
+                ("count", ctypes.c_uint32 * 64), ("enc", ctypes.c_uint32 * 256), ("lut", ctypes.c_uint16 * 1024)]
 
 
 class HuffParams(ctypes.Structure):
-    _fields_ = [("enc_tile_rounds", ctypes.c_uint32), ("hist_blocks", ctypes.c_uint32),
-                ("hist_depth", ctypes.c_uint32), ("dec_block", ctypes.c_uint32)]
+    _fields_ = [("hist_blocks", ctypes.c_uint32), ("hist_depth", ctypes.c_uint32), ("dec_block", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 #: every symbol include/huff.h declares, with (restype, argtypes)
@@ -52,6 +52,7 @@ PROTOTYPES = {
     "huff_build_codebook_device": (_i32, [_vp, _vp, _vp, _vp, _vp]),
     "huff_codebook_upload": (_i32, [_vp, _vp, _vp, _vp]),
     "huff_encode": (_i32, [_vp, _vp, _u64, _vp, _u32, _vp, _u64, _vp, _u32, _vp, _vp, _vp]),
+    "huff_compress": (_i32, [_vp, _vp, _u64, _u32, _vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp]),
     "huff_decode": (_i32, [_vp, _vp, _u64, _vp, _u64, _u32, _vp, _u32, _vp, _vp, _vp, _vp]),
     "huff_copy": (_i32, [_vp, _vp, _vp, _u64, _vp]),
     "huff_abi_sizeof": (_u64, [_int]),

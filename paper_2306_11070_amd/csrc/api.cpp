@@ -15,9 +15,9 @@ struct huff_ctx {
     int num_cus = 256;
     huff_params params{};
     HistState* hist_st = nullptr;
-    EncState* enc_st = nullptr;
-    unsigned long long* lb = nullptr;
+    unsigned long long* lb = nullptr;  // encode look-back words
     uint64_t lb_cap = 0;
+    uint32_t epoch = 0;                // tag of the last encode launch
     int32_t* status = nullptr;
 };
 
@@ -43,7 +43,7 @@ huff_status hip_status(hipError_t e) { return e == hipSuccess ? HUFF_OK : HUFF_E
 
 huff_params defaults(int num_cus) {
     huff_params p;
-    p.enc_tile_rounds = 4;
+    p.reserved = 0;
     p.hist_blocks = (uint32_t)num_cus * 2;
     p.hist_depth = 32;
     p.dec_block = 256;
@@ -51,16 +51,13 @@ huff_params defaults(int num_cus) {
 }
 
 huff_status check_params(const huff_params& p) {
-    if (p.enc_tile_rounds && p.enc_tile_rounds != 1 && p.enc_tile_rounds != 2 && p.enc_tile_rounds != 4 &&
-        p.enc_tile_rounds != 8)
-        return HUFF_E_INVAL;
+    if (p.reserved) return HUFF_E_INVAL;
     if (p.hist_depth && (!is_pow2(p.hist_depth) || p.hist_depth > (uint32_t)kHistMaxDepth)) return HUFF_E_INVAL;
     if (p.dec_block && (p.dec_block < 64 || p.dec_block > 256 || p.dec_block % 64)) return HUFF_E_INVAL;
     return HUFF_OK;
 }
 
 void merge_params(huff_params& dst, const huff_params& src) {
-    if (src.enc_tile_rounds) dst.enc_tile_rounds = src.enc_tile_rounds;
     if (src.hist_blocks) dst.hist_blocks = src.hist_blocks;
     if (src.hist_depth) dst.hist_depth = src.hist_depth;
     if (src.dec_block) dst.dec_block = src.dec_block;
@@ -120,15 +117,9 @@ huff_status huff_ctx_create(int device, const huff_params* params, huff_ctx** ou
         merge_params(c->params, *params);
     }
     bool ok = hipMalloc(&c->hist_st, sizeof(HistState)) == hipSuccess &&
-              hipMalloc(&c->enc_st, sizeof(EncState)) == hipSuccess &&
               hipMalloc(&c->status, 256) == hipSuccess;
     if (ok) ok = hipMemset(c->hist_st, 0, sizeof(HistState)) == hipSuccess &&
-                 hipMemset(c->enc_st, 0, sizeof(EncState)) == hipSuccess &&
                  hipMemset(c->status, 0, 256) == hipSuccess;
-    if (ok) {
-        EncState init{0, 0, 1, 0};
-        ok = hipMemcpy(c->enc_st, &init, sizeof(init), hipMemcpyHostToDevice) == hipSuccess;
-    }
     if (ok) ok = hipDeviceSynchronize() == hipSuccess;
     if (!ok) { huff_ctx_destroy(c); return HUFF_E_NOMEM; }
     *out = c;
@@ -140,7 +131,6 @@ void huff_ctx_destroy(huff_ctx* c) {
     DeviceGuard g(c->device);
     (void)hipDeviceSynchronize();
     if (c->hist_st) (void)hipFree(c->hist_st);
-    if (c->enc_st) (void)hipFree(c->enc_st);
     if (c->lb) (void)hipFree(c->lb);
     if (c->status) (void)hipFree(c->status);
     delete c;
@@ -168,11 +158,8 @@ huff_status huff_ctx_status(huff_ctx* c, int32_t* out, int reset) {
     return HUFF_OK;
 }
 
-huff_status huff_histogram(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint64_t* d_hist, void* stream) {
-    if (!c || !d_hist || (n && !d_in) || n >= kMaxN) return HUFF_E_INVAL;
-    DeviceGuard g(c->device);
-    hipStream_t s = as_stream(stream);
-    if (n == 0) return hip_status(launch_fill_u64(reinterpret_cast<unsigned long long*>(d_hist), 256, 0, s));
+namespace {
+huff_status launch_hist_only(huff_ctx* c, const uint8_t* d_in, uint64_t n, hipStream_t s) {
     uint64_t blocks = std::min<uint64_t>(c->params.hist_blocks, (n + 65535) / 65536);
     blocks = std::max<uint64_t>(blocks, (n >> 31) + 1);  // < 2^31 bytes per workgroup: u32 LDS counters
     const uint64_t nvec = (n + 15) / 16;
@@ -181,11 +168,74 @@ huff_status huff_histogram(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint64_
     HistArgs a;
     a.in = d_in;
     a.n = n;
-    a.out = d_hist;
     a.st = c->hist_st;
     a.depth_log2 = log2u(c->params.hist_depth);
     a.per_block = per_vec * 16;
     return hip_status(launch_histogram(a, (uint32_t)blocks, s));
+}
+
+// Look-back tag for the next encode launch on this context; clears the
+// look-back words (on the stream, before the launch) when the tag wraps.
+huff_status next_epoch(huff_ctx* c, hipStream_t s, uint32_t* out) {
+    if (++c->epoch > kEpochMax) {
+        c->epoch = 1;
+        huff_status st = hip_status(launch_fill_u64(c->lb, c->lb_cap, 0, s));
+        if (st != HUFF_OK) return st;
+    }
+    *out = c->epoch;
+    return HUFF_OK;
+}
+
+huff_status check_encode_args(uint64_t n, const void* d_in, const void* d_words, const void* d_chunk_off,
+                              uint32_t chunk_size, uint32_t sub_size, const void* d_sub_lo) {
+    if (!d_chunk_off || n >= kMaxN) return HUFF_E_INVAL;
+    if (!is_pow2(chunk_size) || chunk_size < 1024 || chunk_size > (64u << 20)) return HUFF_E_INVAL;
+    if (sub_size && (!is_pow2(sub_size) || sub_size < 16 || sub_size > chunk_size || !d_sub_lo)) return HUFF_E_INVAL;
+    if (n && (!d_in || !d_words)) return HUFF_E_INVAL;
+    return HUFF_OK;
+}
+
+huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff_dcb* d_cb, uint32_t chunk_size,
+                              uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off, uint32_t sub_size,
+                              uint32_t* d_sub_lo, int32_t* d_status, hipStream_t s) {
+    if (n == 0) return hip_status(launch_encode_empty(d_chunk_off, sub_size ? d_sub_lo : nullptr, s));
+    const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
+    huff_status st = ensure_lb(c, ntiles);
+    if (st != HUFF_OK) return st;
+    EncArgs a;
+    memset(&a, 0, sizeof(a));
+    st = next_epoch(c, s, &a.epoch);
+    if (st != HUFF_OK) return st;
+    a.files = nullptr;
+    a.one.in = d_in;
+    a.one.n = n;
+    a.one.cb = d_cb;
+    a.one.words = d_words;
+    a.one.nwords = cap_words;
+    a.one.chunk_off = d_chunk_off;
+    a.one.sub_lo = sub_size ? d_sub_lo : nullptr;
+    a.one.status = d_status;
+    a.one.first = 0;
+    a.nfiles = 1;
+    a.chunk_log2 = log2u(chunk_size);
+    a.sub_log2 = sub_size ? log2u(sub_size) : kNoSub;
+    a.epoch_ptr = nullptr;
+    a.ntiles = ntiles;
+    a.lb = c->lb;
+    a.err = c->status;
+    return hip_status(launch_encode(a, s));
+}
+}  // namespace
+
+huff_status huff_histogram(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint64_t* d_hist, void* stream) {
+    if (!c || !d_hist || (n && !d_in) || n >= kMaxN) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    hipStream_t s = as_stream(stream);
+    if (n) {
+        huff_status st = launch_hist_only(c, d_in, n, s);
+        if (st != HUFF_OK) return st;
+    }
+    return hip_status(launch_hist_finalize(c->hist_st, d_hist, s));
 }
 
 // ---- host codebook: tie-ruled Huffman lengths, then canonical codes -------
@@ -288,41 +338,36 @@ huff_status huff_codebook_upload(huff_ctx* c, const huff_codebook* cb, huff_dcb*
 huff_status huff_encode(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff_dcb* d_cb, uint32_t chunk_size,
                         uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off, uint32_t sub_size,
                         uint32_t* d_sub_lo, int32_t* d_status, void* stream) {
-    if (!c || !d_cb || !d_chunk_off || n >= kMaxN) return HUFF_E_INVAL;
-    if (!is_pow2(chunk_size) || chunk_size < 1024 || chunk_size > (64u << 20)) return HUFF_E_INVAL;
-    if (sub_size && (!is_pow2(sub_size) || sub_size < 16 || sub_size > chunk_size || !d_sub_lo)) return HUFF_E_INVAL;
-    if (n && (!d_in || !d_words)) return HUFF_E_INVAL;
+    if (!c || !d_cb) return HUFF_E_INVAL;
+    huff_status st = check_encode_args(n, d_in, d_words, d_chunk_off, chunk_size, sub_size, d_sub_lo);
+    if (st != HUFF_OK) return st;
+    DeviceGuard g(c->device);
+    return launch_encode_one(c, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
+                             d_status, as_stream(stream));
+}
+
+huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t chunk_size, huff_dcb* d_cb,
+                          uint64_t* d_hist, uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off,
+                          uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, void* stream) {
+    if (!c || !d_cb) return HUFF_E_INVAL;
+    huff_status st = check_encode_args(n, d_in, d_words, d_chunk_off, chunk_size, sub_size, d_sub_lo);
+    if (st != HUFF_OK) return st;
     DeviceGuard g(c->device);
     hipStream_t s = as_stream(stream);
-    if (n == 0) return hip_status(launch_encode_empty(d_chunk_off, sub_size ? d_sub_lo : nullptr, s));
-    const uint32_t rounds = c->params.enc_tile_rounds;
-    const uint64_t tile = (uint64_t)rounds * kRoundBytes;
-    const uint64_t ntiles = (n + tile - 1) / tile;
-    huff_status st = ensure_lb(c, ntiles);
-    if (st != HUFF_OK) return st;
-    EncArgs a;
+    if (n) {
+        st = launch_hist_only(c, d_in, n, s);
+        if (st != HUFF_OK) return st;
+    }
+    CbArgs a;
     memset(&a, 0, sizeof(a));
-    a.files = nullptr;
-    a.one.in = d_in;
-    a.one.n = n;
-    a.one.cb = d_cb;
-    a.one.words = d_words;
-    a.one.nwords = cap_words;
-    a.one.chunk_off = d_chunk_off;
-    a.one.sub_lo = sub_size ? d_sub_lo : nullptr;
-    a.one.status = d_status;
-    a.one.first = 0;
-    a.nfiles = 1;
-    a.chunk_log2 = log2u(chunk_size);
-    a.sub_log2 = sub_size ? log2u(sub_size) : kNoSub;
-    a.rounds = rounds;
-    a.ntiles = ntiles;
-    a.st = c->enc_st;
-    a.lb = c->lb;
-    a.lb_cap = c->lb_cap;
-    a.err = c->status;
-    const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)c->num_cus * 4);
-    return hip_status(launch_encode(a, (uint32_t)grid, s));
+    a.acc = c->hist_st;
+    a.hist_out = d_hist;
+    a.out = d_cb;
+    a.err = d_status ? d_status : c->status;
+    st = hip_status(launch_codebook(a, s));
+    if (st != HUFF_OK) return st;
+    return launch_encode_one(c, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
+                             d_status, s);
 }
 
 huff_status huff_decode(huff_ctx* c, const uint32_t* d_words, uint64_t nwords, const uint64_t* d_chunk_off,

@@ -9,9 +9,9 @@
 
 namespace huff {
 
-constexpr int kEncThreads = 256;                 // encode workgroup
-constexpr int kUnitBytes = 16;                   // bytes per thread per encode round
-constexpr int kRoundBytes = kEncThreads * kUnitBytes;  // 4 KiB
+constexpr int kEncThreads = 512;                 // encode workgroup
+constexpr int kEncUnit = 32;                     // input bytes per encode thread
+constexpr int kEncTile = kEncThreads * kEncUnit; // 16 KiB per tile
 constexpr int kCbThreads = 256;                  // codebook workgroup (one per file)
 constexpr int kHistThreads = 512;
 constexpr int kHistMaxDepth = 32;
@@ -25,21 +25,13 @@ constexpr uint64_t kValueMask = (1ull << 44) - 1;
 constexpr uint64_t kFlagAgg = 1ull << 62;
 constexpr uint64_t kFlagPre = 2ull << 62;
 
-// Self-resetting encode workspace (device).  ticket/done return to 0 and
-// epoch advances at the end of every launch; status[] entries are tagged
-// with the epoch that wrote them, so no clearing pass is needed.
-struct EncState {
-    uint32_t ticket;
-    uint32_t done;
-    uint32_t epoch;  // 1..kEpochMax
-    uint32_t pad;
-};
-
-// Self-resetting histogram accumulator (device).
+// Histogram accumulator (device).  Workgroup w adds into copy
+// w % kHistCopies, which spreads same-address atomics; the kernel that
+// consumes the counts (finalize or codebook) sums the copies and zeroes them
+// for the next launch.
+constexpr int kHistCopies = 32;
 struct HistState {
-    unsigned long long acc[256];
-    uint32_t done;
-    uint32_t pad[63];
+    unsigned long long acc[kHistCopies][256];
 };
 
 // One stream / file as the kernels see it.  Single calls pass one by value;
@@ -63,11 +55,10 @@ struct EncArgs {
     uint32_t nfiles;
     uint32_t chunk_log2;
     uint32_t sub_log2;      // kNoSub if no sub index
-    uint32_t rounds;        // 4 KiB rounds per tile
-    uint64_t ntiles;        // total over all files
-    EncState* st;
+    uint32_t epoch;         // tag of this launch's look-back words (1..kEpochMax)
+    const uint32_t* epoch_ptr;  // if set, the tag is read from here instead
+    uint64_t ntiles;        // total over all files (= grid size)
     unsigned long long* lb; // look-back status words, >= ntiles
-    uint64_t lb_cap;
     int32_t* err;           // fallback status word
 };
 
@@ -85,14 +76,15 @@ struct DecArgs {
 struct HistArgs {
     const uint8_t* in;
     uint64_t n;
-    uint64_t* out;
     HistState* st;
     uint32_t depth_log2;
     uint64_t per_block;     // bytes per workgroup (multiple of 16)
 };
 
 struct CbArgs {
-    const uint64_t* hist;   // from-histogram mode (null in from-lengths mode)
+    const uint64_t* hist;   // histogram input (from-histogram mode) ...
+    HistState* acc;         // ... or the histogram accumulator, summed and zeroed here
+    uint64_t* hist_out;     // optional copy of the summed histogram (accumulator mode)
     huff_dcb* out;
     int32_t* err;
     uint32_t from_lengths;
@@ -101,8 +93,10 @@ struct CbArgs {
 
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s);
+hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s);
 hipError_t launch_codebook(const CbArgs& a, hipStream_t s);
-hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_encode(const EncArgs& a, hipStream_t s);
+hipError_t launch_epoch_bump(uint32_t* epoch, unsigned long long* lb, uint64_t cap, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo, hipStream_t s);
 hipError_t launch_decode(const DecArgs& a, uint32_t block, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);

@@ -59,7 +59,6 @@ __device__ __forceinline__ uint32_t find_file(const FileDesc* files, uint32_t nf
 // ============================================================== histogram
 __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
     __shared__ uint32_t sh[256 * kHistMaxDepth];
-    __shared__ int s_last;
     const uint32_t dl = a.depth_log2, depth = 1u << dl;
     const uint32_t tid = threadIdx.x;
     for (uint32_t i = tid; i < 256u * depth; i += blockDim.x) sh[i] = 0;
@@ -101,17 +100,19 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
     for (uint32_t v = tid; v < 256; v += stride) {
         uint32_t s = 0;
         for (uint32_t r = 0; r < depth; ++r) s += sh[(v << dl) | ((r + v) & (depth - 1))];
-        if (s) atomicAdd(&a.st->acc[v], (unsigned long long)s);
+        if (s) atomicAdd(&a.st->acc[blockIdx.x % kHistCopies][v], (unsigned long long)s);
     }
-    __threadfence();
-    __syncthreads();
-    if (tid == 0) s_last = atomicAdd(&a.st->done, 1u) == gridDim.x - 1;
-    __syncthreads();
-    if (s_last) {
-        __threadfence();
-        for (uint32_t v = tid; v < 256; v += stride) a.out[v] = atomicExch(&a.st->acc[v], 0ull);
-        if (tid == 0) atomicExch(&a.st->done, 0u);
+}
+
+// Sums the accumulator copies into d_hist and zeroes them for the next launch.
+__global__ __launch_bounds__(256) void k_hist_finalize(HistState* st, uint64_t* out) {
+    const uint32_t v = threadIdx.x;
+    unsigned long long t = 0;
+    for (int c = 0; c < kHistCopies; ++c) {
+        t += st->acc[c][v];
+        st->acc[c][v] = 0;
     }
+    out[v] = t;
 }
 
 hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s) {
@@ -119,13 +120,57 @@ hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_hist_finalize, dim3(1), dim3(256), 0, s, st, out);
+    return hipGetLastError();
+}
+
 // =============================================================== codebook
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
+    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64), hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bitonic sort of 256 u64 keys, one per thread of a 256-thread workgroup;
+// thread t returns the t-th smallest.  Exchanges inside a wave use lane
+// shuffles; only the three stages that cross waves go through LDS.
+__device__ uint64_t sort256(uint64_t key, unsigned long long* tmp) {
+    const uint32_t t = threadIdx.x;
+    for (uint32_t k = 2; k <= 256; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            uint64_t other;
+            if (j >= 64) {
+                tmp[t] = key;
+                __syncthreads();
+                other = tmp[t ^ j];
+                __syncthreads();
+            } else {
+                other = shfl_xor_u64(key, (int)j);
+            }
+            const bool keepMin = ((t & j) == 0) == ((t & k) == 0);
+            key = keepMin ? (key < other ? key : other) : (key < other ? other : key);
+        }
+    }
+    return key;
+}
+
 // One workgroup of 256 threads; thread v owns byte value v.
+//
+// Code lengths follow the merge rule (two smallest (weight, id) nodes ->
+// one node of their summed weight), computed in rounds instead of one merge
+// at a time: with s0 the sum of the two smallest queued nodes, every queued
+// node of weight <= s0 precedes all nodes this round creates, so the first
+// 2*floor(c/2) of those c nodes, taken in merged (weight, id) order, pair up
+// exactly as the one-at-a-time merge pairs them.  Leaves are queued in
+// (count, value) order, internal nodes in creation order (never decreasing),
+// and on equal weight a leaf precedes an internal node and an older node a
+// newer one.
 __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
-    __shared__ unsigned long long s_h[256];
-    __shared__ unsigned long long s_w[512];  // node weights: sorted leaves, then internal nodes
-    __shared__ uint16_t s_par[512];
+    __shared__ unsigned long long s_w[512];  // node weights: sorted leaves [0,K), internal nodes [K, 2K-1)
+    __shared__ unsigned long long s_tmp[256];
+    __shared__ uint16_t s_par[512], s_m[512];
     __shared__ uint16_t s_d[512], s_p[512];
+    __shared__ uint8_t s_sym[256];            // leaf rank -> byte
     __shared__ uint8_t s_len[256];
     __shared__ uint8_t s_sorted[256];
     __shared__ uint32_t s_cnt[64], s_fidx[64];
@@ -135,48 +180,83 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
     const uint32_t v = threadIdx.x;
     uint64_t h = 0;
     uint32_t myLen = 0;
+    int32_t status = HUFF_OK;
     if (v == 0) { s_tot = 0; s_n = 0; s_max = 0; }
     if (v < 64) s_cnt[v] = 0;
-    s_sorted[v] = 0;
     if (!a.from_lengths) {
-        h = a.hist[v];
-        s_h[v] = h;
-        __syncthreads();
-        const int K = __syncthreads_count(h != 0);
-        uint32_t rank = 0;
-        if (h) {
-            for (uint32_t u = 0; u < 256; ++u) {
-                const uint64_t hu = s_h[u];
-                rank += (hu != 0) & ((hu < h) | ((hu == h) & (u < v)));
+        if (a.acc) {
+            for (int c = 0; c < kHistCopies; ++c) {
+                h += a.acc->acc[c][v];
+                a.acc->acc[c][v] = 0;
             }
-            s_w[rank] = h;
+            if (a.hist_out) a.hist_out[v] = h;
+        } else {
+            h = a.hist[v];
+        }
+        if (__syncthreads_or(h >> 56)) status = HUFF_E_INVAL;  // counts must fit the sort key
+        const uint32_t K = (uint32_t)__syncthreads_count(h != 0);
+        // leaves in (count, value) order; absent bytes sort first as key 0
+        const uint64_t key = sort256(h && status == HUFF_OK ? (h << 8) | v : 0ull, s_tmp);
+        const uint32_t off = 256 - K;
+        if (v >= off) {
+            s_w[v - off] = key >> 8;
+            s_sym[v - off] = (uint8_t)(key & 0xffu);
         }
         __syncthreads();
-        if (K == 1) {
+        if (status != HUFF_OK) {
+            // leave every length 0
+        } else if (K == 1) {
             myLen = h ? 1u : 0u;
         } else if (K >= 2) {
-            if (v == 0) {
-                // Two queues: leaves s_w[0..K) ascending, internal nodes
-                // s_w[K..K+made) in creation order (never decreasing).  On
-                // equal weight the leaf (smaller id) is taken first.
-                uint32_t li = 0, qi = 0;
-                for (uint32_t m = 0; m < (uint32_t)K - 1; ++m) {
-                    uint32_t id[2];
-                    uint64_t w[2];
-#pragma unroll
-                    for (int t = 0; t < 2; ++t) {
-                        const bool leaf = li < (uint32_t)K && (qi >= m || s_w[li] <= s_w[K + qi]);
-                        id[t] = leaf ? li : K + qi;
-                        w[t] = s_w[id[t]];
-                        li += leaf;
-                        qi += !leaf;
+            uint32_t li = 0, qi = 0, m = 0;  // leaf head, internal head, internal nodes made
+            while (m < K - 1) {
+                // s0: sum of the two smallest queued nodes (leaf first on ties)
+                const uint64_t kInf = ~0ull;
+                const uint64_t l0 = li < K ? s_w[li] : kInf, l1 = li + 1 < K ? s_w[li + 1] : kInf;
+                const uint64_t i0 = qi < m ? s_w[K + qi] : kInf, i1 = qi + 1 < m ? s_w[K + qi + 1] : kInf;
+                uint64_t s0;
+                if (l0 <= i0) s0 = l0 + (l1 <= i0 ? l1 : i0);
+                else s0 = i0 + (l0 <= i1 ? l0 : i1);
+                const bool leafIn = li + v < K && s_w[li + v] <= s0;
+                const bool intIn = qi + v < m && s_w[K + qi + v] <= s0;
+                const uint32_t cL = (uint32_t)__syncthreads_count(leafIn);
+                const uint32_t cI = (uint32_t)__syncthreads_count(intIn);
+                const uint32_t pairs = (cL + cI) >> 1;
+                // merged position of each node taking part
+                uint32_t posL = ~0u;
+                if (leafIn) {
+                    const uint64_t key2 = s_w[li + v];
+                    uint32_t lo = 0, hi = cI;  // internal nodes strictly lighter
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (s_w[K + qi + mid] < key2) lo = mid + 1; else hi = mid;
                     }
-                    s_w[K + m] = w[0] + w[1];
-                    s_par[id[0]] = (uint16_t)(K + m);
-                    s_par[id[1]] = (uint16_t)(K + m);
+                    posL = v + lo;
+                    if (posL < 2 * pairs) s_m[posL] = (uint16_t)(li + v);
                 }
+                if (intIn) {
+                    const uint64_t key2 = s_w[K + qi + v];
+                    uint32_t lo = 0, hi = cL;  // leaves at most as heavy
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (s_w[li + mid] <= key2) lo = mid + 1; else hi = mid;
+                    }
+                    const uint32_t pos = v + lo;
+                    if (pos < 2 * pairs) s_m[pos] = (uint16_t)(K + qi + v);
+                }
+                const uint32_t nl = (uint32_t)__syncthreads_count(posL < 2 * pairs);
+                if (v < pairs) {
+                    const uint32_t x = s_m[2 * v], y = s_m[2 * v + 1];
+                    const uint32_t id = K + m + v;
+                    s_w[id] = s_w[x] + s_w[y];
+                    s_par[x] = (uint16_t)id;
+                    s_par[y] = (uint16_t)id;
+                }
+                __syncthreads();
+                li += nl;
+                qi += 2 * pairs - nl;
+                m += pairs;
             }
-            __syncthreads();
             // depths by pointer jumping: d = distance to p, p -> p's ancestor
             const uint32_t nodes = 2 * K - 1, root = nodes - 1;
             for (uint32_t i = v; i < nodes; i += 256) {
@@ -203,16 +283,19 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
                 }
                 __syncthreads();
             }
-            if (h) myLen = s_d[rank];
+            s_len[v] = 0;
+            __syncthreads();
+            if (v < K) s_len[s_sym[v]] = (uint8_t)s_d[v];
+            __syncthreads();
+            myLen = h ? s_len[v] : 0u;
         }
         atomicAdd(&s_tot, (unsigned long long)(h * myLen));
         atomicAdd(&s_n, (unsigned long long)h);
     } else {
         myLen = a.len[v];
     }
-    s_len[v] = (uint8_t)myLen;
     __syncthreads();
-    int32_t status = HUFF_OK;
+    s_len[v] = (uint8_t)myLen;
     if (myLen) {
         atomicMax(&s_max, myLen);
         if (myLen < 64) atomicAdd(&s_cnt[myLen], 1u);
@@ -231,15 +314,22 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
         s_fidx[v] = fidx;
         s_first[v] = fc;
     }
+    // present bytes in (length, value) order: position -> canonical code
+    const uint32_t K2 = (uint32_t)__syncthreads_count(myLen != 0 && myLen < 64);
+    const uint64_t key = sort256(myLen && myLen < 64 ? ((uint64_t)myLen << 8) | v : 0ull, s_tmp);
+    s_sorted[v] = 0;
     __syncthreads();
-    uint64_t code = 0;
-    if (myLen && myLen < 64) {
-        uint32_t r = 0;
-        for (uint32_t u = 0; u < v; ++u) r += s_len[u] == myLen;
-        code = s_first[myLen] + r;
-        s_sorted[s_fidx[myLen] + r] = (uint8_t)v;
+    uint64_t* codes = reinterpret_cast<uint64_t*>(s_w);  // reuse: code per byte value
+    codes[v] = 0;
+    __syncthreads();
+    if (v >= 256 - K2) {
+        const uint32_t i = v - (256 - K2);
+        const uint32_t sym = (uint32_t)(key & 0xffu), l = (uint32_t)(key >> 8);
+        s_sorted[i] = (uint8_t)sym;
+        codes[sym] = s_first[l] + (i - s_fidx[l]);
     }
     __syncthreads();
+    const uint64_t code = codes[v];
     huff_dcb* d = a.out;
     const uint32_t lutBits = maxLen < HUFF_LUT_BITS ? maxLen : HUFF_LUT_BITS;
     d->len[v] = (uint8_t)myLen;
@@ -265,9 +355,7 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
         d->lut[p] = e;
     }
     if (v == 0) {
-        uint32_t k = 0;
-        for (uint32_t l = 1; l < 64; ++l) k += s_cnt[l];
-        d->nsym = k;
+        d->nsym = K2;
         d->max_len = maxLen;
         d->lut_bits = lutBits;
         d->status = status;
@@ -283,313 +371,350 @@ hipError_t launch_codebook(const CbArgs& a, hipStream_t s) {
 }
 
 // ================================================================= encode
-constexpr int kBufWords = 3200;  // >= one 4 KiB round at 24 bits/byte, one wave's units at 63 bits/byte
+// One workgroup per tile of 16 KiB (512 threads x 32 bytes), tile index =
+// blockIdx.  A tile's first stream bit comes from a decoupled look-back over
+// the earlier tiles' published bit counts.  The wait is bounded: if a
+// predecessor has published nothing after kSpinLimit polls, the waiting wave
+// counts that tile's bits itself and publishes them on its behalf (the same
+// value the owner will publish), so progress never depends on the order in
+// which workgroups are dispatched.  No atomic read-modify-write is used.
+//
+// Output words are owned by the thread whose bit range holds the word's last
+// bit; the bits of the owner's first word that precede its range belong to
+// the previous thread (read from that thread's LDS slot) or, for the first
+// thread of a tile, are re-derived from the 32 input bytes before the tile.
+// The final partial word of a stream is written by its last thread.  No two
+// threads write the same word.
+constexpr int kSlotWords = 16;   // private LDS words per thread: 32 bytes x 16 bits
+constexpr int kEncWaves = kEncThreads / 64;
+constexpr int kSpinLimit = 64;
 
-__device__ __forceinline__ uint4 load_unit(const uint8_t* in, uint64_t q, uint64_t n, bool aligned) {
+__device__ __forceinline__ uint4 load16(const uint8_t* in, uint64_t q, uint64_t n, bool aligned) {
     if (aligned && q + 16 <= n) return *reinterpret_cast<const uint4*>(in + q);
-    uint32_t w[4] = {0, 0, 0, 0};
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-        if (q + i < n) w[i >> 2] |= (uint32_t)in[q + i] << (8 * (i & 3));
-    return make_uint4(w[0], w[1], w[2], w[3]);
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t b = q + i < n ? (uint32_t)in[q + i] : 0u;
+        const uint32_t sh = 8 * (i & 3);
+        if (i < 4) w0 |= b << sh;
+        else if (i < 8) w1 |= b << sh;
+        else if (i < 12) w2 |= b << sh;
+        else w3 |= b << sh;
+    }
+    return make_uint4(w0, w1, w2, w3);
 }
 
-// Append `len` (<= 32) bits of `c`; full 32-bit words go to the LDS buffer.
-struct Packer {
-    uint64_t acc;
-    uint32_t na;  // valid low bits in acc (< 32 between appends)
-    uint32_t wi;  // LDS word that receives the next full word
-    __device__ __forceinline__ void put(uint64_t c, uint32_t len, uint32_t* buf) {
-        acc = (acc << len) | c;
-        na += len;
-        if (na >= 32) {
-            na -= 32;
-            atomicOr(&buf[wi++], (uint32_t)(acc >> na));
-        }
-    }
-    __device__ __forceinline__ void finish(uint32_t* buf) {
-        if (na) atomicOr(&buf[wi], (uint32_t)(acc << (32 - na)));
-    }
-};
+__device__ __forceinline__ uint32_t byte32(const uint4& x0, const uint4& x1, int i) {
+    return i < 16 ? byte_of(x0, i) : byte_of(x1, i - 16);
+}
 
-template <int R, bool kBatch>
+// Bits of a whole (full) tile, counted by one wave.
+__device__ uint32_t wave_tile_bits(const uint8_t* in, uint64_t tstart, bool aligned, const uint8_t* s_len) {
+    uint32_t sum = 0;
+    const int lane = __lane_id();
+    for (int v = 0; v < kEncTile / (64 * 16); ++v) {
+        const uint4 x = load16(in, tstart + (uint64_t)(v * 64 + lane) * 16, ~0ull, aligned);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) sum += s_len[byte_of(x, i)];
+    }
+    return (uint32_t)wave_sum_u64(sum);
+}
+
+template <bool kBatch>
 __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
+    __shared__ uint32_t s_slot[kSlotWords * kEncThreads];  // word k of thread t at [k*T + t]; tile bytes (generic)
     __shared__ uint32_t s_enc[256];
     __shared__ unsigned long long s_code[256];
     __shared__ uint8_t s_len[256];
     __shared__ uint8_t s_prev[32];
-    __shared__ uint32_t s_buf[kBufWords];
-    __shared__ uint32_t s_wsum[4][R];
+    __shared__ uint32_t s_L[kEncThreads];
+    __shared__ uint32_t s_wsum[kEncWaves];
+    __shared__ unsigned long long s_lbp[kEncWaves], s_lbi[kEncWaves], s_lsum[kEncWaves];
     __shared__ unsigned long long s_excl;
-    __shared__ uint32_t s_ticket, s_carry, s_maxlen;
-    __shared__ int s_last, s_wrap;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint32_t epoch = __hip_atomic_load(&a.st->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t g = blockIdx.x;
+    FileDesc f;
+    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, g)];
+    else f = a.one;
+    const uint32_t epoch = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
     const uint64_t tagE = (uint64_t)epoch << 44;
-    const huff_dcb* loaded = nullptr;
-    constexpr uint64_t kTile = (uint64_t)R * kRoundBytes;
+    const uint64_t j = g - f.first;
+    const uint64_t n = f.n;
+    const uint64_t tstart = j * (uint64_t)kEncTile;
+    const uint64_t q0 = tstart + (uint64_t)tid * kEncUnit;
+    const uint32_t nv = q0 >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q0);
+    const bool aligned = ((uintptr_t)f.in & 15u) == 0;
+    const uint4 x0 = load16(f.in, q0, n, aligned);
+    const uint4 x1 = load16(f.in, q0 + 16, n, aligned);
+    if (tid < 32 && j > 0) s_prev[tid] = f.in[tstart - 32 + tid];
+    const uint32_t maxLen = f.cb->max_len;
+    const bool fast = maxLen <= 16;
+    if (tid < 256) {
+        s_len[tid] = f.cb->len[tid];
+        if (fast) s_enc[tid] = f.cb->enc[tid];
+        else s_code[tid] = f.cb->code[tid];
+    }
+    __syncthreads();
 
-    for (uint32_t i = tid; i < kBufWords; i += kEncThreads) s_buf[i] = 0;
-
-    for (;;) {
-        if (tid == 0) s_ticket = atomicAdd(&a.st->ticket, 1u);
-        __syncthreads();
-        const uint64_t g = s_ticket;
-        if (g >= a.ntiles) break;
-        FileDesc f;
-        if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, g)];
-        else f = a.one;
-        const uint64_t j = g - f.first;
-        const uint64_t tstart = j * kTile;
-        const uint64_t n = f.n;
-        const bool lastTile = tstart + kTile >= n;
-        const bool aligned = ((uintptr_t)f.in & 15u) == 0;
-        int32_t* err = f.status ? f.status : a.err;
-
-        // issue the tile's loads before the (possibly) serialising table load
-        uint4 x[R];
+    // 1) pack into the private slot (fast) or count bits (generic)
+    uint32_t L = 0, mid = 0, nwp = 0;
+    bool missing = false;
+    if (fast) {
+        uint64_t acc = 0;
+        uint32_t na = 0, wi = 0;
+        auto put = [&](uint32_t e) {
+            const uint32_t len = e & 0xffu;
+            missing |= len == 0;
+            acc = (acc << len) | (e >> 8);
+            na += len;
+            if (na >= 32) {
+                na -= 32;
+                s_slot[wi * kEncThreads + tid] = (uint32_t)(acc >> na);
+                ++wi;
+            }
+        };
+        if (nv == kEncUnit) {
 #pragma unroll
-        for (int r = 0; r < R; ++r) x[r] = load_unit(f.in, tstart + (uint64_t)(r * kEncThreads + tid) * 16, n, aligned);
-        if (tid < 32 && j > 0) s_prev[tid] = f.in[tstart - 32 + tid];
-
-        if (f.cb != loaded) {
-            s_enc[tid] = f.cb->enc[tid];
-            s_code[tid] = f.cb->code[tid];
-            s_len[tid] = f.cb->len[tid];
-            if (tid == 0) s_maxlen = f.cb->max_len;
-            loaded = f.cb;
+            for (int i = 0; i < 16; ++i) put(s_enc[byte_of(x0, i)]);
+            mid = wi * 32 + na;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) put(s_enc[byte_of(x1, i)]);
+        } else {
+            for (uint32_t i = 0; i < nv; ++i) {
+                put(s_enc[byte32(x0, x1, (int)i)]);
+                if (i == 15) mid = wi * 32 + na;
+            }
         }
-        __syncthreads();
-        const uint32_t maxLen = s_maxlen;
-        const bool generic = maxLen > 24;
+        L = wi * 32 + na;
+        nwp = wi;
+        if (na) {
+            s_slot[wi * kEncThreads + tid] = (uint32_t)(acc << (32 - na));
+            ++nwp;
+        }
+    } else {
+        reinterpret_cast<uint4*>(s_slot)[2 * tid] = x0;
+        reinterpret_cast<uint4*>(s_slot)[2 * tid + 1] = x1;
+        for (uint32_t i = 0; i < nv; ++i) {
+            const uint32_t l = s_len[byte32(x0, x1, (int)i)];
+            missing |= l == 0;
+            L += l;
+            if (i == 15) mid = L;
+        }
+    }
+    if (missing) report(f.status, a.err, HUFF_E_INVAL);
 
-        // 1) code bits per 16-byte unit
-        uint32_t usum[R];
-        bool missing = false;
+    // 2) workgroup exclusive scan of per-thread bit counts
+    s_L[tid] = L;
+    const uint32_t incl = wave_incl_scan(L);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, agg = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint64_t q = tstart + (uint64_t)(r * kEncThreads + tid) * 16;
-            const uint32_t nv = q >= n ? 0u : (uint32_t)min<uint64_t>(16, n - q);
-            uint32_t s = 0;
-            if (nv == 16) {
+    for (int w = 0; w < kEncWaves; ++w) {
+        const uint32_t ws = s_wsum[w];
+        agg += ws;
+        before += w < wave ? ws : 0u;
+    }
+    const uint32_t excl = before + incl - L;
+
+    // 3) decoupled look-back for the tile's first stream bit.  The whole
+    //    workgroup reads kEncThreads predecessors per round trip.
+    unsigned long long* lb = a.lb + (g - j);  // this file's look-back words
+    if (j == 0) {
+        if (tid == 0) {
+            __hip_atomic_store(&lb[0], kFlagPre | tagE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_excl = 0;
+        }
+    } else {
+        if (tid == 0)
+            __hip_atomic_store(&lb[j], kFlagAgg | tagE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t sum = 0;
+        int64_t pos = (int64_t)j - 1;
+        int spins = 0;
+        for (;;) {
+            const int64_t idx = pos - tid;
+            uint64_t st = 0;
+            bool valid = true, pre = true;
+            if (idx >= 0) {
+                st = __hip_atomic_load(&lb[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint32_t fl = (uint32_t)(st >> 62);
+                valid = fl != 0 && (uint32_t)((st >> 44) & kEpochMax) == epoch;
+                pre = valid && fl == 2;
+            }
+            const uint64_t bp = __ballot(pre), bi = __ballot(!valid);
+            if (lane == 0) {
+                s_lbp[wave] = bp;
+                s_lbi[wave] = bi;
+            }
+            __syncthreads();
+            // nearest prefix-carrying predecessor (lowest thread index), and
+            // whether every predecessor up to it has published
+            int first = kEncThreads;
+            bool waitMore = false;
 #pragma unroll
-                for (int i = 0; i < 16; ++i) {
-                    const uint32_t l = s_len[byte_of(x[r], i)];
-                    s += l;
-                    missing |= l == 0;
-                }
-            } else {
-                for (uint32_t i = 0; i < nv; ++i) {
-                    const uint32_t l = s_len[byte_of(x[r], i)];
-                    s += l;
-                    missing |= l == 0;
+            for (int w = 0; w < kEncWaves; ++w) {
+                const uint64_t p = s_lbp[w], iv = s_lbi[w];
+                if (first == kEncThreads) {
+                    const uint64_t upto = p ? ((p & (~p + 1)) << 1) - 1 : ~0ull;  // bits up to the lowest set one
+                    if (iv & upto) waitMore = true;
+                    if (p) first = 64 * w + __ffsll((unsigned long long)p) - 1;
                 }
             }
-            usum[r] = s;
-        }
-        if (missing) report(f.status, a.err, HUFF_E_INVAL);
-
-        // 2) workgroup scan of unit totals in unit order (round-major)
-        uint32_t incl[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) incl[r] = wave_incl_scan(usum[r]);
-        if (lane == 63) {
-#pragma unroll
-            for (int r = 0; r < R; ++r) s_wsum[wave][r] = incl[r];
-        }
-        __syncthreads();
-        uint32_t uexcl[R], rstart[R + 1];
-        uint32_t base = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            uint32_t before = 0, tot = 0;
-#pragma unroll
-            for (int w = 0; w < 4; ++w) {
-                const uint32_t ws = s_wsum[w][r];
-                tot += ws;
-                before += w < wave ? ws : 0u;
-            }
-            rstart[r] = base;
-            uexcl[r] = base + before + incl[r] - usum[r];
-            base += tot;
-        }
-        rstart[R] = base;
-        const uint32_t agg = base;
-
-        // 3) decoupled look-back for the tile's first stream bit
-        if (j == 0) {
-            if (tid == 0) {
-                __hip_atomic_store(&a.lb[g], kFlagPre | tagE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_excl = 0;
-            }
-        } else if (wave == 0) {
-            if (lane == 0)
-                __hip_atomic_store(&a.lb[g], kFlagAgg | tagE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            uint64_t excl = 0;
-            int64_t pos = (int64_t)j - 1;
-            for (;;) {
-                const int64_t idx = pos - lane;
-                uint64_t st = 0;
-                bool valid = true, pre = true;
-                if (idx >= 0) {
-                    st = __hip_atomic_load(&a.lb[g - j + (uint64_t)idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                    const uint32_t fl = (uint32_t)(st >> 62);
-                    valid = fl != 0 && (uint32_t)((st >> 44) & kEpochMax) == epoch;
-                    pre = valid && fl == 2;
-                }
-                const uint64_t bp = __ballot(pre);
-                const uint64_t bi = __ballot(!valid);
-                const int first = bp ? __ffsll((unsigned long long)bp) - 1 : 64;
-                const uint64_t upto = first >= 63 ? ~0ull : ((2ull << first) - 1);
-                if (bi & upto) {
-                    __builtin_amdgcn_s_sleep(1);
+            if (waitMore) {
+                __syncthreads();
+                if (++spins < kSpinLimit) {
+                    __builtin_amdgcn_s_sleep(2);
                     continue;
                 }
-                excl += wave_sum_u64((lane <= first && idx >= 0) ? (st & kValueMask) : 0ull);
-                if (first < 64) break;
-                pos -= 64;
-            }
-            if (lane == 0) {
-                __hip_atomic_store(&a.lb[g], kFlagPre | tagE | (excl + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                s_excl = excl;
-            }
-        }
-        __syncthreads();
-        const uint64_t S = s_excl;
-        if (tid == 0) {
-            // bits of the shared first word that belong to earlier bytes,
-            // recomputed from the 32 bytes before the tile
-            const uint32_t rb = (uint32_t)(S & 31);
-            uint32_t carry = 0;
-            if (rb) {
-                uint64_t acc = 0;
-                uint32_t nb = 0;
-                int k = 31;
-                while (nb < rb && k >= 0) {
-                    const uint32_t b = s_prev[k--];
-                    acc |= (uint64_t)s_code[b] << nb;
-                    nb += s_len[b];
-                }
-                carry = (uint32_t)(acc & ((1u << rb) - 1)) << (32 - rb);
-            }
-            s_carry = carry;
-        }
-        // 4) segment index and decode index
+                // count the nearest silent predecessor's bits ourselves and
+                // publish them on its behalf
+                int z = kEncThreads;
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const uint64_t q = tstart + (uint64_t)(r * kEncThreads + tid) * 16;
-            if (q < n) {
-                const uint64_t bp = S + uexcl[r];
-                if ((q & ((1ull << a.chunk_log2) - 1)) == 0) f.chunk_off[q >> a.chunk_log2] = bp;
-                if (a.sub_log2 != kNoSub && (q & ((1ull << a.sub_log2) - 1)) == 0) f.sub_lo[q >> a.sub_log2] = (uint32_t)bp;
-            }
-        }
-        if (lastTile && tid == 0) {
-            const uint64_t T = S + agg;
-            f.chunk_off[(n + (1ull << a.chunk_log2) - 1) >> a.chunk_log2] = T;
-            if (a.sub_log2 != kNoSub) f.sub_lo[(n + (1ull << a.sub_log2) - 1) >> a.sub_log2] = (uint32_t)T;
-            if (((T + 31) >> 5) > f.nwords) report(f.status, a.err, HUFF_E_CAPACITY);
-        }
-        __syncthreads();
-
-        // 5) pack into LDS and stream out complete words
-        uint32_t carry = s_carry;
-        const int wavesPerPass = generic ? 1 : 4;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            for (int wp = 0; wp < 4; wp += wavesPerPass) {
-                uint32_t pre = 0, mid = 0;
-                for (int w = 0; w < 4; ++w) {
-                    const uint32_t ws = s_wsum[w][r];
-                    pre += w < wp ? ws : 0u;
-                    mid += (w >= wp && w < wp + wavesPerPass) ? ws : 0u;
-                }
-                const uint64_t A = S + rstart[r] + pre, B = A + mid;
-                const uint64_t w0 = A >> 5;
-                if (tid == 0 && carry) atomicOr(&s_buf[0], carry);
-                if (wave >= wp && wave < wp + wavesPerPass) {
-                    const uint64_t q = tstart + (uint64_t)(r * kEncThreads + tid) * 16;
-                    const uint32_t nv = q >= n ? 0u : (uint32_t)min<uint64_t>(16, n - q);
-                    const uint32_t lbit = (uint32_t)(S + uexcl[r] - (w0 << 5));
-                    Packer pk{0, lbit & 31, lbit >> 5};
-                    if (!generic && nv == 16) {
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) {
-                            const uint32_t e = s_enc[byte_of(x[r], i)];
-                            pk.put(e >> 8, e & 0xffu, s_buf);
-                        }
-                    } else if (!generic) {
-                        for (uint32_t i = 0; i < nv; ++i) {
-                            const uint32_t e = s_enc[byte_of(x[r], i)];
-                            pk.put(e >> 8, e & 0xffu, s_buf);
-                        }
-                    } else {
-                        for (uint32_t i = 0; i < nv; ++i) {
-                            const uint32_t b = byte_of(x[r], i);
-                            const uint32_t l = s_len[b];
-                            const uint64_t c = s_code[b];
-                            if (l > 32) {
-                                pk.put(c >> 32, l - 32, s_buf);
-                                pk.put(c & 0xffffffffull, 32, s_buf);
-                            } else {
-                                pk.put(c, l, s_buf);
-                            }
-                        }
+                for (int w = kEncWaves - 1; w >= 0; --w)
+                    if (s_lbi[w]) z = 64 * w + __ffsll((unsigned long long)s_lbi[w]) - 1;
+                const uint64_t tz = (uint64_t)(pos - z);
+                if (wave == 0) {
+                    const uint32_t bits = wave_tile_bits(f.in, tz * kEncTile, aligned, s_len);
+                    if (lane == 0) {
+                        const uint64_t cur = __hip_atomic_load(&lb[tz], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        const bool curValid = (cur >> 62) != 0 && (uint32_t)((cur >> 44) & kEpochMax) == epoch;
+                        if (!curValid)
+                            __hip_atomic_store(&lb[tz], kFlagAgg | tagE | (uint64_t)bits, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
                     }
-                    pk.finish(s_buf);
                 }
                 __syncthreads();
-                const uint32_t nfull = (uint32_t)((B >> 5) - w0);
-                for (uint32_t k = tid; k < nfull; k += kEncThreads)
-                    if (w0 + k < f.nwords) f.words[w0 + k] = s_buf[k];
-                carry = (B & 31) ? s_buf[nfull] : 0u;
-                __syncthreads();
-                for (uint32_t k = tid; k <= nfull; k += kEncThreads) s_buf[k] = 0;
-                __syncthreads();
+                spins = 0;
+                continue;
             }
+            const uint64_t part = wave_sum_u64((tid <= first && idx >= 0) ? (st & kValueMask) : 0ull);
+            if (lane == 0) s_lsum[wave] = part;
+            __syncthreads();
+#pragma unroll
+            for (int w = 0; w < kEncWaves; ++w) sum += s_lsum[w];
+            __syncthreads();
+            if (first < kEncThreads) break;
+            pos -= kEncThreads;
         }
-        if (lastTile && tid == 0) {
-            const uint64_t T = S + agg;
-            if ((T & 31) && (T >> 5) < f.nwords) f.words[T >> 5] = carry;
+        if (tid == 0) {
+            __hip_atomic_store(&lb[j], kFlagPre | tagE | (sum + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_excl = sum;
+        }
+    }
+    __syncthreads();
+    const uint64_t S = s_excl;
+    const uint64_t b = S + excl, e = b + L;
+    const uint32_t sh = (uint32_t)(b & 31);
+    const bool lastThread = nv > 0 && q0 + kEncUnit >= n;
+
+    // 4) segment index and decode index
+    if (nv) {
+        if ((q0 & ((1ull << a.chunk_log2) - 1)) == 0) f.chunk_off[q0 >> a.chunk_log2] = b;
+        if (a.sub_log2 != kNoSub) {
+            if ((q0 & ((1ull << a.sub_log2) - 1)) == 0) f.sub_lo[q0 >> a.sub_log2] = (uint32_t)b;
+            if (a.sub_log2 == 4 && nv > 16) f.sub_lo[(q0 >> 4) + 1] = (uint32_t)(b + mid);
+        }
+    }
+    if (lastThread) {
+        f.chunk_off[(n + (1ull << a.chunk_log2) - 1) >> a.chunk_log2] = e;
+        if (a.sub_log2 != kNoSub) f.sub_lo[(n + (1ull << a.sub_log2) - 1) >> a.sub_log2] = (uint32_t)e;
+        if (((e + 31) >> 5) > f.nwords) report(f.status, a.err, HUFF_E_CAPACITY);
+    }
+
+    // 5) the bits before b that share b's word, right-aligned
+    uint32_t prefix = 0;
+    if (sh && nv) {
+        if (tid > 0 && fast && s_L[tid - 1] >= sh) {
+            const uint32_t Lp = s_L[tid - 1];
+            const uint32_t q = Lp - sh, i = q >> 5, o = q & 31;
+            const uint32_t nwprev = (Lp + 31) >> 5;
+            const uint64_t hi = s_slot[i * kEncThreads + tid - 1];
+            const uint64_t lo = i + 1 < nwprev ? s_slot[(i + 1) * kEncThreads + tid - 1] : 0u;
+            prefix = (uint32_t)((((hi << 32) | lo) << o) >> 32) >> (32 - sh);
+        } else {
+            // re-derive from the bytes just before this thread's unit
+            uint64_t acc = 0;
+            uint32_t nb = 0;
+            for (int k = 31; k >= 0 && nb < sh; --k) {
+                const uint32_t v = tid == 0 ? s_prev[k] : reinterpret_cast<const uint8_t*>(s_slot)[(tid - 1) * kEncUnit + k];
+                const uint64_t c = fast ? (uint64_t)(s_enc[v] >> 8) : s_code[v];
+                acc |= c << nb;
+                nb += s_len[v];
+            }
+            prefix = (uint32_t)acc & ((1u << sh) - 1);
         }
     }
 
-    // the last workgroup out resets the ticket and done counters and
-    // advances the epoch (clearing the look-back words when it wraps)
-    __syncthreads();
-    if (tid == 0) {
-        __threadfence();
-        s_last = atomicAdd(&a.st->done, 1u) == gridDim.x - 1;
-        s_wrap = 0;
-        if (s_last) {
-            uint32_t e = epoch + 1;
-            if (e > kEpochMax) { e = 1; s_wrap = 1; }
-            atomicExch(&a.st->ticket, 0u);
-            atomicExch(&a.st->done, 0u);
-            atomicExch(&a.st->epoch, e);
+    // 6) write the owned words
+    const uint64_t w0 = b >> 5;
+    if (fast) {
+        uint32_t nw = (uint32_t)((e >> 5) - w0);
+        if (lastThread && (e & 31)) ++nw;
+        uint32_t prevw = prefix;
+        for (uint32_t k = 0; k < nw; ++k) {
+            const uint32_t cur = k < nwp ? s_slot[k * kEncThreads + tid] : 0u;
+            const uint32_t v = __builtin_amdgcn_alignbit(prevw, cur, sh);
+            if (w0 + k < f.nwords) f.words[w0 + k] = v;
+            prevw = cur;
         }
+    } else if (nv) {
+        uint64_t acc = prefix;
+        uint32_t na = sh;
+        uint64_t w = w0;
+        auto put = [&](uint64_t c, uint32_t len) {
+            acc = (acc << len) | c;
+            na += len;
+            if (na >= 32) {
+                na -= 32;
+                if (w < f.nwords) f.words[w] = (uint32_t)(acc >> na);
+                ++w;
+            }
+        };
+        for (uint32_t i = 0; i < nv; ++i) {
+            const uint32_t v = byte32(x0, x1, (int)i);
+            const uint32_t l = s_len[v];
+            const uint64_t c = s_code[v];
+            if (l > 32) {
+                put(c >> 32, l - 32);
+                put(c & 0xffffffffull, 32);
+            } else {
+                put(c, l);
+            }
+        }
+        if (lastThread && na && w < f.nwords) f.words[w] = (uint32_t)(acc << (32 - na));
     }
-    __syncthreads();
-    if (s_last && s_wrap)
-        for (uint64_t i = tid; i < a.lb_cap; i += kEncThreads) a.lb[i] = 0;
 }
 
-template <int R>
-static hipError_t launch_encode_r(const EncArgs& a, uint32_t grid, hipStream_t s) {
-    if (a.files) hipLaunchKernelGGL((k_encode<R, true>), dim3(grid), dim3(kEncThreads), 0, s, a);
-    else hipLaunchKernelGGL((k_encode<R, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
+hipError_t launch_encode(const EncArgs& a, hipStream_t s) {
+    if (a.files) hipLaunchKernelGGL(k_encode<true>, dim3((uint32_t)a.ntiles), dim3(kEncThreads), 0, s, a);
+    else hipLaunchKernelGGL(k_encode<false>, dim3((uint32_t)a.ntiles), dim3(kEncThreads), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s) {
-    switch (a.rounds) {
-        case 1: return launch_encode_r<1>(a, grid, s);
-        case 2: return launch_encode_r<2>(a, grid, s);
-        case 4: return launch_encode_r<4>(a, grid, s);
-        case 8: return launch_encode_r<8>(a, grid, s);
-        default: return hipErrorInvalidValue;
+// Advances a device-side epoch word (for launches replayed from a graph,
+// whose kernel arguments cannot change); clears the look-back words when the
+// epoch wraps.
+__global__ void k_epoch_bump(uint32_t* epoch, unsigned long long* lb, uint64_t cap) {
+    __shared__ uint32_t s_next;
+    if (threadIdx.x == 0) {
+        uint32_t e = *epoch + 1;
+        if (e > kEpochMax || e == 0) e = 0;
+        s_next = e;
     }
+    __syncthreads();
+    if (s_next == 0) {
+        for (uint64_t i = threadIdx.x; i < cap; i += blockDim.x) lb[i] = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) *epoch = 1;
+    } else if (threadIdx.x == 0) {
+        *epoch = s_next;
+    }
+}
+
+hipError_t launch_epoch_bump(uint32_t* epoch, unsigned long long* lb, uint64_t cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_epoch_bump, dim3(1), dim3(1024), 0, s, epoch, lb, cap);
+    return hipGetLastError();
 }
 
 __global__ void k_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo) {
@@ -671,87 +796,152 @@ __device__ __forceinline__ uint64_t peek64(const uint32_t* w, uint64_t nwords, u
     return s ? (hi << s) | (a2 >> (32 - s)) : hi;
 }
 
-template <bool kBatch>
-__global__ __launch_bounds__(256) void k_decode(DecArgs a) {
-    __shared__ uint16_t s_lut[1 << HUFF_LUT_BITS];
-    __shared__ unsigned long long s_first[64];
-    __shared__ uint32_t s_cnt[64], s_fidx[64];
-    __shared__ uint8_t s_sorted[256];
+// Canonical tables of one codebook, staged in LDS by every decode workgroup.
+struct DecTables {
+    uint16_t lut[1 << HUFF_LUT_BITS];
+    unsigned long long first[64];
+    uint32_t cnt[64], fidx[64];
+    uint8_t sorted[256];
+};
 
-    const uint64_t item = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    FileDesc f;
-    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, (uint64_t)blockIdx.x * blockDim.x)];
-    else f = a.one;
-    const huff_dcb* cb = f.cb;
-    const uint32_t lutBits = cb->lut_bits, maxLen = cb->max_len;
-    for (uint32_t i = threadIdx.x; i < (1u << lutBits); i += blockDim.x) s_lut[i] = cb->lut[i];
+__device__ __forceinline__ void load_tables(DecTables& t, const huff_dcb* cb, uint32_t lutBits) {
+    for (uint32_t i = threadIdx.x; i < (1u << lutBits); i += blockDim.x) t.lut[i] = cb->lut[i];
     for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
-        s_first[i] = cb->first_code[i];
-        s_cnt[i] = cb->count[i];
-        s_fidx[i] = cb->first_index[i];
+        t.first[i] = cb->first_code[i];
+        t.cnt[i] = cb->count[i];
+        t.fidx[i] = cb->first_index[i];
     }
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) s_sorted[i] = cb->sorted_sym[i];
-    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) t.sorted[i] = cb->sorted_sym[i];
+}
 
-    const uint64_t j = item - f.first;
-    const uint64_t n = f.n;
+// Codes longer than the table: canonical search on the top 32 window bits.
+// Returns sym | len << 8, or 0 if no code matches.
+__device__ __noinline__ uint32_t decode_long(const DecTables& t, uint32_t top, uint32_t lutBits, uint32_t maxLen) {
+    for (uint32_t l = lutBits + 1; l <= maxLen; ++l) {
+        const uint64_t c = top >> (32 - l);
+        if (c - t.first[l] < t.cnt[l]) return t.sorted[t.fidx[l] + (uint32_t)(c - t.first[l])] | (l << 8);
+    }
+    return 0;
+}
+
+// Reader over words staged in LDS (word 0 = the first staged stream word).
+struct LdsReader {
+    const uint32_t* s;
+    uint32_t lim, nxt, pre;
+    uint64_t win;
+    uint32_t avail;
+    __device__ __forceinline__ uint32_t get(uint32_t i) const { return i < lim ? s[i] : 0u; }
+    __device__ __forceinline__ void init(const uint32_t* s_, uint32_t lim_, uint32_t bit) {
+        s = s_;
+        lim = lim_;
+        const uint32_t wi = bit >> 5, sk = bit & 31;
+        win = (((uint64_t)get(wi) << 32) | get(wi + 1)) << sk;
+        avail = 64 - sk;
+        nxt = wi + 2;
+        pre = get(nxt);
+    }
+    __device__ __forceinline__ void refill() {
+        if (avail < 32) {
+            win |= (uint64_t)pre << (32 - avail);
+            avail += 32;
+            pre = get(++nxt);
+        }
+    }
+};
+
+// One symbol from a reader whose window holds >= 32 valid bits after refill.
+template <class Rd, typename U>
+__device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad, U& used) {
+    r.refill();
+    const uint32_t top = (uint32_t)(r.win >> 32);
+    uint32_t e = t.lut[top >> (32 - lutBits)];
+    if ((e >> 8) == 0) {
+        e = decode_long(t, top, lutBits, maxLen);
+        if (e == 0) { bad = true; e = 1u << 8; }
+    }
+    const uint32_t len = e >> 8;
+    r.win <<= len;
+    r.avail -= len;
+    used += len;
+    return e & 0xffu;
+}
+
+// Codes longer than 32 bits: canonical search on a 64-bit peek from memory.
+__device__ void decode_generic(const FileDesc& f, const DecTables& t, uint32_t maxLen, uint64_t start, uint64_t nsym,
+                               uint8_t* out, bool& bad, uint64_t& used) {
+    uint64_t pos = start;
+    for (uint64_t i = 0; i < nsym; ++i) {
+        const uint64_t top = peek64(f.words, f.nwords, pos);
+        uint32_t len = 0, sym = 0;
+        for (uint32_t l = 1; l <= maxLen; ++l) {
+            const uint64_t c = top >> (64 - l);
+            if (c - t.first[l] < t.cnt[l]) {
+                sym = t.sorted[t.fidx[l] + (uint32_t)(c - t.first[l])];
+                len = l;
+                break;
+            }
+        }
+        if (len == 0) { bad = true; len = 1; }
+        out[i] = (uint8_t)sym;
+        pos += len;
+        used += len;
+    }
+}
+
+// Start/end stream bits of decode item j (a sub-block, or a chunk without sub index).
+__device__ __forceinline__ void item_bits(const FileDesc& f, const DecArgs& a, uint64_t j, uint64_t nitems,
+                                          uint64_t& start, uint64_t& end) {
     const uint32_t il = a.item_log2, cl = a.chunk_log2;
-    const uint64_t nitems = (n + (1ull << il) - 1) >> il;
-    if (j >= nitems) return;
-    const uint64_t nchunks = (n + (1ull << cl) - 1) >> cl;
-    uint64_t start, end;
     if (a.use_sub) {
-        const uint64_t c = (j << il) >> cl;
-        const uint64_t base = f.chunk_off[c];
+        const uint64_t base = f.chunk_off[(j << il) >> cl];
         start = base + (uint32_t)(f.sub_lo[j] - (uint32_t)base);
         if (j + 1 == nitems) {
-            end = f.chunk_off[nchunks];
+            end = f.chunk_off[(f.n + (1ull << cl) - 1) >> cl];
         } else {
-            const uint64_t c2 = ((j + 1) << il) >> cl;
-            const uint64_t b2 = f.chunk_off[c2];
+            const uint64_t b2 = f.chunk_off[((j + 1) << il) >> cl];
             end = b2 + (uint32_t)(f.sub_lo[j + 1] - (uint32_t)b2);
         }
     } else {
         start = f.chunk_off[j];
         end = f.chunk_off[j + 1];
     }
+}
+
+// Direct decoder: one lane per item, words read straight from memory.  Used
+// for chunk-only indexes and sub-blocks that the staged kernel does not take.
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_decode(DecArgs a) {
+    __shared__ DecTables t;
+    const uint64_t item = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    FileDesc f;
+    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, (uint64_t)blockIdx.x * blockDim.x)];
+    else f = a.one;
+    const huff_dcb* cb = f.cb;
+    const uint32_t lutBits = cb->lut_bits, maxLen = cb->max_len;
+    load_tables(t, cb, lutBits);
+    __syncthreads();
+
+    const uint64_t j = item - f.first;
+    const uint64_t n = f.n;
+    const uint32_t il = a.item_log2;
+    const uint64_t nitems = (n + (1ull << il) - 1) >> il;
+    if (j >= nitems) return;
+    uint64_t start, end;
+    item_bits(f, a, j, nitems, start, end);
     const uint64_t first = j << il;
     const uint64_t nsym = min<uint64_t>(1ull << il, n - first);
     uint8_t* out = f.out + first;
     bool bad = start > end || end > f.nwords * 32ull || maxLen == 0 || maxLen > HUFF_MAX_CODE_LEN;
     uint64_t used = 0;
-
     if (!bad && maxLen <= 32) {
         BitReader br;
         br.init(f.words, f.nwords, start);
-        const uint32_t lutShift = 32 - lutBits;
-        auto one = [&]() -> uint32_t {
-            br.refill();
-            const uint32_t top = (uint32_t)(br.win >> 32);
-            const uint32_t e = s_lut[top >> lutShift];
-            uint32_t len = e >> 8, sym = e & 0xffu;
-            if (len == 0) {
-                for (uint32_t l = lutBits + 1; l <= maxLen; ++l) {
-                    const uint64_t c = top >> (32 - l);
-                    if (c - s_first[l] < s_cnt[l]) {
-                        sym = s_sorted[s_fidx[l] + (uint32_t)(c - s_first[l])];
-                        len = l;
-                        break;
-                    }
-                }
-                if (len == 0) { bad = true; len = 1; }
-            }
-            br.win <<= len;
-            br.avail -= len;
-            used += len;
-            return sym;
-        };
         const uint64_t groups = nsym >> 4;
         const bool vec_ok = (((uintptr_t)out) & 15u) == 0;
         for (uint64_t gi = 0; gi < groups; ++gi) {
             uint32_t o[4] = {0, 0, 0, 0};
 #pragma unroll
-            for (int i = 0; i < 16; ++i) o[i >> 2] |= one() << (8 * (i & 3));
+            for (int i = 0; i < 16; ++i) o[i >> 2] |= dec1(br, t, lutBits, maxLen, bad, used) << (8 * (i & 3));
             if (vec_ok) {
                 reinterpret_cast<uint4*>(out)[gi] = make_uint4(o[0], o[1], o[2], o[3]);
             } else {
@@ -759,31 +949,132 @@ __global__ __launch_bounds__(256) void k_decode(DecArgs a) {
                 for (int i = 0; i < 16; ++i) out[gi * 16 + i] = (uint8_t)(o[i >> 2] >> (8 * (i & 3)));
             }
         }
-        for (uint64_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)one();
+        for (uint64_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)dec1(br, t, lutBits, maxLen, bad, used);
     } else if (!bad) {
-        // codes longer than 32 bits: canonical search on a 64-bit peek
-        uint64_t pos = start;
-        for (uint64_t i = 0; i < nsym; ++i) {
-            const uint64_t top = peek64(f.words, f.nwords, pos);
-            uint32_t len = 0, sym = 0;
-            for (uint32_t l = 1; l <= maxLen; ++l) {
-                const uint64_t c = top >> (64 - l);
-                if (c - s_first[l] < s_cnt[l]) {
-                    sym = s_sorted[s_fidx[l] + (uint32_t)(c - s_first[l])];
-                    len = l;
-                    break;
+        decode_generic(f, t, maxLen, start, nsym, out, bad, used);
+    }
+    if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
+}
+
+// Staged decoder for sub-blocks of S bytes (S = 32..256).  Each wave takes 64
+// consecutive sub-blocks: their stream bits are contiguous, so the wave loads
+// them once into LDS with coalesced 16-byte loads, then every lane decodes its
+// sub-block from LDS and stores every 16 decoded bytes with one 16-byte store.  A wave whose bits exceed the buffer (more than 8 bits per
+// byte on average) reads memory directly instead.
+template <int S, bool kBatch>
+__global__ __launch_bounds__(256) void k_decode_staged(DecArgs a) {
+    constexpr uint32_t kInWords = 64 * S / 4 + 8;
+    __shared__ uint32_t s_in[4][kInWords];
+    __shared__ DecTables t;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    FileDesc f;
+    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, (uint64_t)blockIdx.x * 256)];
+    else f = a.one;
+    const huff_dcb* cb = f.cb;
+    const uint32_t lutBits = cb->lut_bits, maxLen = cb->max_len;
+    load_tables(t, cb, lutBits);
+
+    const uint64_t n = f.n;
+    const uint64_t nitems = (n + S - 1) / S;
+    const uint64_t j0 = (uint64_t)blockIdx.x * 256 + wave * 64 - f.first;  // first item of this wave
+    const uint64_t j = j0 + lane;
+    const bool active = j < nitems;
+    uint64_t start = 0, end = 0;
+    if (active) item_bits(f, a, j, nitems, start, end);
+    // the wave's stream range, from its first and last active lanes
+    bool staged = false;
+    uint64_t base = 0;
+    if (j0 < nitems) {
+        const uint32_t la = (uint32_t)min<uint64_t>(63, nitems - 1 - j0);
+        const uint64_t ws = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(start >> 32), 0) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((uint32_t)start, 0);
+        const uint64_t we = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(end >> 32), la) << 32) |
+                            (uint32_t)__builtin_amdgcn_readlane((uint32_t)end, la);
+        base = (ws >> 5) & ~3ull;
+        const uint64_t cnt = ((we + 31) >> 5) - base;
+        staged = we >= ws && cnt + 4 <= kInWords && maxLen <= 32;
+        if (staged) {
+            const uint32_t nv = (uint32_t)((cnt + 3) >> 2);
+            const uint4* src = reinterpret_cast<const uint4*>(f.words) + (base >> 2);
+            uint4* dst = reinterpret_cast<uint4*>(s_in[wave]);
+            for (uint32_t v = lane; v < nv; v += 64) {
+                const uint64_t wi = base + 4ull * v;
+                uint4 q;
+                if (wi + 4 <= f.nwords) {
+                    q = src[v];
+                } else {
+                    q.x = wi < f.nwords ? f.words[wi] : 0u;
+                    q.y = wi + 1 < f.nwords ? f.words[wi + 1] : 0u;
+                    q.z = wi + 2 < f.nwords ? f.words[wi + 2] : 0u;
+                    q.w = wi + 3 < f.nwords ? f.words[wi + 3] : 0u;
                 }
+                dst[v] = q;
             }
-            if (len == 0) { bad = true; len = 1; }
-            out[i] = (uint8_t)sym;
-            pos += len;
-            used += len;
         }
+    }
+    __syncthreads();
+    if (!active) return;
+
+    const uint64_t first = j * S;
+    const uint32_t nsym = (uint32_t)min<uint64_t>(S, n - first);
+    uint8_t* out = f.out + first;
+    bool bad = start > end || end > f.nwords * 32ull || maxLen == 0 || maxLen > HUFF_MAX_CODE_LEN;
+    if (bad) {
+        report(f.status, a.err, HUFF_E_CORRUPT);
+        return;
+    }
+    if (maxLen > 32) {
+        uint64_t used = 0;
+        decode_generic(f, t, maxLen, start, nsym, out, bad, used);
+        if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
+        return;
+    }
+    uint32_t used = 0;
+    auto run = [&](auto& rd) {
+        const uint32_t groups = nsym >> 4;
+#pragma unroll 1
+        for (uint32_t gi = 0; gi < groups; ++gi) {
+            uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o0 |= dec1(rd, t, lutBits, maxLen, bad, used) << (8 * i);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o1 |= dec1(rd, t, lutBits, maxLen, bad, used) << (8 * i);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o2 |= dec1(rd, t, lutBits, maxLen, bad, used) << (8 * i);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) o3 |= dec1(rd, t, lutBits, maxLen, bad, used) << (8 * i);
+            reinterpret_cast<uint4*>(out)[gi] = make_uint4(o0, o1, o2, o3);
+        }
+        for (uint32_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)dec1(rd, t, lutBits, maxLen, bad, used);
+    };
+    if (staged) {
+        LdsReader rd;
+        rd.init(s_in[wave], kInWords, (uint32_t)(start - (base << 5)));
+        run(rd);
+    } else {
+        BitReader rd;
+        rd.init(f.words, f.nwords, start);
+        run(rd);
     }
     if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
 }
 
 hipError_t launch_decode(const DecArgs& a, uint32_t block, hipStream_t s) {
+    const uint32_t sub = 1u << a.item_log2;
+    if (a.use_sub && sub >= 32 && sub <= 256) {
+        const uint64_t blocks = (a.nitems + 255) / 256;
+#define HUFF_STAGED(SZ)                                                                                      \
+    if (sub == SZ) {                                                                                         \
+        if (a.files) hipLaunchKernelGGL((k_decode_staged<SZ, true>), dim3((uint32_t)blocks), dim3(256), 0, s, a); \
+        else hipLaunchKernelGGL((k_decode_staged<SZ, false>), dim3((uint32_t)blocks), dim3(256), 0, s, a);      \
+        return hipGetLastError();                                                                            \
+    }
+        HUFF_STAGED(32)
+        HUFF_STAGED(64)
+        HUFF_STAGED(128)
+        HUFF_STAGED(256)
+#undef HUFF_STAGED
+    }
     const uint64_t blocks = (a.nitems + block - 1) / block;
     if (a.files) hipLaunchKernelGGL(k_decode<true>, dim3((uint32_t)blocks), dim3(block), 0, s, a);
     else hipLaunchKernelGGL(k_decode<false>, dim3((uint32_t)blocks), dim3(block), 0, s, a);

@@ -128,7 +128,7 @@ def _codebook_cases():
 
 
 def _lut_expect(ln, code, lut_bits):
-    exp = np.zeros(1 << 12, dtype=np.uint16)
+    exp = np.zeros(1 << 10, dtype=np.uint16)
     for p in range(1 << lut_bits):
         for v in range(256):
             l = int(ln[v])
@@ -151,7 +151,7 @@ def test_codebook_device(P, codec, case):
     assert np.array_equal(np.ctypeslib.as_array(d.code).astype(np.uint64), code)
     assert d.nsym == int(np.count_nonzero(ln)) and d.max_len == int(ln.max())
     assert d.total_bits == oracle.total_bits(h, ln) and d.n == int(h.sum())
-    assert d.lut_bits == min(int(ln.max()), 12)
+    assert d.lut_bits == min(int(ln.max()), 10)
     keyed = sorted((int(ln[v]), v) for v in range(256) if ln[v])
     assert list(np.frombuffer(bytes(d.sorted_sym), np.uint8)[: len(keyed)]) == [v for _, v in keyed]
     assert np.array_equal(np.ctypeslib.as_array(d.lut), _lut_expect(ln, code, d.lut_bits))
@@ -196,6 +196,13 @@ def _roundtrip(codec, a, chunk, sub):
     x = dev(a)
     c = codec.compress(x, chunk, sub, status=st)
     _check_status(st)
+    # the separate calls give the same result as the fused one
+    h2 = codec.histogram(x)
+    d2 = codec.build_codebook_device(h2, status=st)
+    w2, o2, s2 = codec.encode(x, d2, chunk, sub, status=st)
+    _check_status(st)
+    assert torch.equal(h2, c["hist"]) and torch.equal(o2, c["chunk_off"])
+    assert torch.equal(d2, c["dcb"])
     r = oracle.compress(a, chunk, sub=sub if sub else None)
     nw = r["words"].size
     assert np.array_equal(host_u64(c["hist"]), r["hist"])
@@ -220,12 +227,13 @@ def test_encode_decode_parity(codec, kind, n, chunk, sub):
     _roundtrip(codec, _data(kind, n), chunk, sub)
 
 
-@pytest.mark.parametrize("rounds", [1, 2, 4, 8])
+@pytest.mark.parametrize("hist", [(1, 1), (7, 4), (512, 32)])
 @pytest.mark.parametrize("dec_block", [64, 256])
-def test_launch_shapes_same_output(P, rounds, dec_block):
-    _say(f"launch shapes rounds={rounds} dec_block={dec_block}")
-    c = P.Codec(0, dict(enc_tile_rounds=rounds, dec_block=dec_block))
-    _roundtrip(c, _data("markov", 333_333, seed=rounds), 2048, 64)
+@pytest.mark.parametrize("sub", [0, 16, 32, 64, 128, 256, 512])
+def test_launch_shapes_same_output(P, hist, dec_block, sub):
+    _say(f"launch shapes hist={hist} dec_block={dec_block} sub={sub}")
+    c = P.Codec(0, dict(hist_blocks=hist[0], hist_depth=hist[1], dec_block=dec_block))
+    _roundtrip(c, _data("markov", 333_333, seed=hist[0]), 2048, sub)
     c.close()
 
 
