@@ -107,7 +107,7 @@ typedef struct huff_params {
     uint32_t hist_blocks;     /* histogram workgroups (persistent grid) */
     uint32_t hist_depth;      /* histogram replicas per workgroup (1..32, power of 2) */
     uint32_t dec_block;       /* direct-decode workgroup size (64, 128, 192 or 256) */
-    uint32_t reserved;        /* must be 0 */
+    uint32_t enc_blocks_per_cu; /* persistent encode workgroups per compute unit (1..16) */
 } huff_params;
 
 typedef struct huff_ctx huff_ctx;

@@ -34,7 +34,7 @@ class HuffDcb(ctypes.Structure):
 
 class HuffParams(ctypes.Structure):
     _fields_ = [("hist_blocks", ctypes.c_uint32), ("hist_depth", ctypes.c_uint32), ("dec_block", ctypes.c_uint32),
-                ("reserved", ctypes.c_uint32)]
+                ("enc_blocks_per_cu", ctypes.c_uint32)]
 
 
 #: every symbol include/huff.h declares, with (restype, argtypes)

@@ -15,9 +15,12 @@ struct huff_ctx {
     int num_cus = 256;
     huff_params params{};
     HistState* hist_st = nullptr;
-    unsigned long long* lb = nullptr;  // encode look-back words
-    uint64_t lb_cap = 0;
-    uint32_t epoch = 0;                // tag of the last encode launch
+    // encode tile workspaces, sized for tile_cap tiles
+    uint16_t* tile_hist = nullptr;        // [tile_cap][256]
+    uint32_t* tile_bits = nullptr;        // [tile_cap]
+    uint32_t* tile_local = nullptr;       // [tile_cap]
+    unsigned long long* blk_total = nullptr;  // [tile_cap / 1024 + 1]
+    uint64_t tile_cap = 0;
     int32_t* status = nullptr;
 };
 
@@ -43,15 +46,15 @@ huff_status hip_status(hipError_t e) { return e == hipSuccess ? HUFF_OK : HUFF_E
 
 huff_params defaults(int num_cus) {
     huff_params p;
-    p.reserved = 0;
+    p.enc_blocks_per_cu = 4;
     p.hist_blocks = (uint32_t)num_cus * 2;
-    p.hist_depth = 32;
+    p.hist_depth = 16;
     p.dec_block = 256;
     return p;
 }
 
 huff_status check_params(const huff_params& p) {
-    if (p.reserved) return HUFF_E_INVAL;
+    if (p.enc_blocks_per_cu > 16) return HUFF_E_INVAL;
     if (p.hist_depth && (!is_pow2(p.hist_depth) || p.hist_depth > (uint32_t)kHistMaxDepth)) return HUFF_E_INVAL;
     if (p.dec_block && (p.dec_block < 64 || p.dec_block > 256 || p.dec_block % 64)) return HUFF_E_INVAL;
     return HUFF_OK;
@@ -61,22 +64,31 @@ void merge_params(huff_params& dst, const huff_params& src) {
     if (src.hist_blocks) dst.hist_blocks = src.hist_blocks;
     if (src.hist_depth) dst.hist_depth = src.hist_depth;
     if (src.dec_block) dst.dec_block = src.dec_block;
+    if (src.enc_blocks_per_cu) dst.enc_blocks_per_cu = src.enc_blocks_per_cu;
 }
 
-// Grows the look-back array to hold `tiles` entries.  Waits for the device
-// first: kernels queued earlier may still use the old array.
-huff_status ensure_lb(huff_ctx* ctx, uint64_t tiles) {
-    if (tiles <= ctx->lb_cap) return HUFF_OK;
-    uint64_t cap = std::max<uint64_t>(tiles, 1024);
-    cap = std::max(cap, ctx->lb_cap * 2);
+// Grows the per-tile workspaces to hold `tiles` tiles.  Waits for the
+// device first: kernels queued earlier may still use the old buffers.
+huff_status ensure_tiles(huff_ctx* ctx, uint64_t tiles) {
+    if (tiles <= ctx->tile_cap) return HUFF_OK;
+    uint64_t cap = std::max<uint64_t>(tiles, 4096);
+    cap = std::max(cap, ctx->tile_cap * 2);
     if (hipDeviceSynchronize() != hipSuccess) return HUFF_E_HIP;
-    if (ctx->lb) (void)hipFree(ctx->lb);
-    ctx->lb = nullptr;
-    ctx->lb_cap = 0;
-    if (hipMalloc(&ctx->lb, cap * sizeof(unsigned long long)) != hipSuccess) return HUFF_E_NOMEM;
-    if (hipMemset(ctx->lb, 0, cap * sizeof(unsigned long long)) != hipSuccess) return HUFF_E_HIP;
-    if (hipDeviceSynchronize() != hipSuccess) return HUFF_E_HIP;
-    ctx->lb_cap = cap;
+    (void)hipFree(ctx->tile_hist);
+    (void)hipFree(ctx->tile_bits);
+    (void)hipFree(ctx->tile_local);
+    (void)hipFree(ctx->blk_total);
+    ctx->tile_hist = nullptr;
+    ctx->tile_bits = ctx->tile_local = nullptr;
+    ctx->blk_total = nullptr;
+    ctx->tile_cap = 0;
+    const uint64_t blocks = cap / kScanTilesPerBlock + 1;
+    if (hipMalloc(&ctx->tile_hist, cap * 256 * sizeof(uint16_t)) != hipSuccess ||
+        hipMalloc(&ctx->tile_bits, cap * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&ctx->tile_local, cap * sizeof(uint32_t)) != hipSuccess ||
+        hipMalloc(&ctx->blk_total, blocks * sizeof(unsigned long long)) != hipSuccess)
+        return HUFF_E_NOMEM;
+    ctx->tile_cap = cap;
     return HUFF_OK;
 }
 
@@ -131,7 +143,10 @@ void huff_ctx_destroy(huff_ctx* c) {
     DeviceGuard g(c->device);
     (void)hipDeviceSynchronize();
     if (c->hist_st) (void)hipFree(c->hist_st);
-    if (c->lb) (void)hipFree(c->lb);
+    (void)hipFree(c->tile_hist);
+    (void)hipFree(c->tile_bits);
+    (void)hipFree(c->tile_local);
+    (void)hipFree(c->blk_total);
     if (c->status) (void)hipFree(c->status);
     delete c;
 }
@@ -159,31 +174,20 @@ huff_status huff_ctx_status(huff_ctx* c, int32_t* out, int reset) {
 }
 
 namespace {
-huff_status launch_hist_only(huff_ctx* c, const uint8_t* d_in, uint64_t n, hipStream_t s) {
-    uint64_t blocks = std::min<uint64_t>(c->params.hist_blocks, (n + 65535) / 65536);
+huff_status launch_hist_only(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint16_t* tile_hist, hipStream_t s) {
+    const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
+    uint64_t blocks = std::min<uint64_t>(c->params.hist_blocks, ntiles);
     blocks = std::max<uint64_t>(blocks, (n >> 31) + 1);  // < 2^31 bytes per workgroup: u32 LDS counters
-    const uint64_t nvec = (n + 15) / 16;
-    const uint64_t per_vec = (nvec + blocks - 1) / blocks;
-    blocks = (nvec + per_vec - 1) / per_vec;
+    const uint64_t tpb = (ntiles + blocks - 1) / blocks;
+    blocks = (ntiles + tpb - 1) / tpb;
     HistArgs a;
     a.in = d_in;
     a.n = n;
     a.st = c->hist_st;
+    a.tile_hist = tile_hist;
     a.depth_log2 = log2u(c->params.hist_depth);
-    a.per_block = per_vec * 16;
+    a.tiles_per_block = tpb;
     return hip_status(launch_histogram(a, (uint32_t)blocks, s));
-}
-
-// Look-back tag for the next encode launch on this context; clears the
-// look-back words (on the stream, before the launch) when the tag wraps.
-huff_status next_epoch(huff_ctx* c, hipStream_t s, uint32_t* out) {
-    if (++c->epoch > kEpochMax) {
-        c->epoch = 1;
-        huff_status st = hip_status(launch_fill_u64(c->lb, c->lb_cap, 0, s));
-        if (st != HUFF_OK) return st;
-    }
-    *out = c->epoch;
-    return HUFF_OK;
 }
 
 huff_status check_encode_args(uint64_t n, const void* d_in, const void* d_words, const void* d_chunk_off,
@@ -195,17 +199,31 @@ huff_status check_encode_args(uint64_t n, const void* d_in, const void* d_words,
     return HUFF_OK;
 }
 
+// Tile offsets (from the per-tile histograms when `from_hist`, else from a
+// bit-counting pass over the input), then the encode itself.
 huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff_dcb* d_cb, uint32_t chunk_size,
                               uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off, uint32_t sub_size,
-                              uint32_t* d_sub_lo, int32_t* d_status, hipStream_t s) {
+                              uint32_t* d_sub_lo, int32_t* d_status, bool from_hist, hipStream_t s) {
     if (n == 0) return hip_status(launch_encode_empty(d_chunk_off, sub_size ? d_sub_lo : nullptr, s));
     const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
-    huff_status st = ensure_lb(c, ntiles);
+    huff_status st;
+    if (!from_hist) {
+        st = ensure_tiles(c, ntiles);
+        if (st != HUFF_OK) return st;
+        st = hip_status(launch_tile_bits(d_in, n, d_cb, c->tile_bits, s));
+        if (st != HUFF_OK) return st;
+    }
+    ScanArgs sa;
+    sa.tile_hist = from_hist ? c->tile_hist : nullptr;
+    sa.tile_bits = from_hist ? nullptr : c->tile_bits;
+    sa.cb = d_cb;
+    sa.ntiles = ntiles;
+    sa.tile_local = c->tile_local;
+    sa.blk_total = c->blk_total;
+    st = hip_status(launch_tile_scan(sa, s));
     if (st != HUFF_OK) return st;
     EncArgs a;
     memset(&a, 0, sizeof(a));
-    st = next_epoch(c, s, &a.epoch);
-    if (st != HUFF_OK) return st;
     a.files = nullptr;
     a.one.in = d_in;
     a.one.n = n;
@@ -219,11 +237,12 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
     a.nfiles = 1;
     a.chunk_log2 = log2u(chunk_size);
     a.sub_log2 = sub_size ? log2u(sub_size) : kNoSub;
-    a.epoch_ptr = nullptr;
     a.ntiles = ntiles;
-    a.lb = c->lb;
+    a.tile_local = c->tile_local;
+    a.blk_total = c->blk_total;
     a.err = c->status;
-    return hip_status(launch_encode(a, s));
+    const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)c->num_cus * c->params.enc_blocks_per_cu);
+    return hip_status(launch_encode(a, (uint32_t)grid, s));
 }
 }  // namespace
 
@@ -232,7 +251,7 @@ huff_status huff_histogram(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint64_
     DeviceGuard g(c->device);
     hipStream_t s = as_stream(stream);
     if (n) {
-        huff_status st = launch_hist_only(c, d_in, n, s);
+        huff_status st = launch_hist_only(c, d_in, n, nullptr, s);
         if (st != HUFF_OK) return st;
     }
     return hip_status(launch_hist_finalize(c->hist_st, d_hist, s));
@@ -343,7 +362,7 @@ huff_status huff_encode(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff
     if (st != HUFF_OK) return st;
     DeviceGuard g(c->device);
     return launch_encode_one(c, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
-                             d_status, as_stream(stream));
+                             d_status, false, as_stream(stream));
 }
 
 huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t chunk_size, huff_dcb* d_cb,
@@ -355,7 +374,9 @@ huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t
     DeviceGuard g(c->device);
     hipStream_t s = as_stream(stream);
     if (n) {
-        st = launch_hist_only(c, d_in, n, s);
+        st = ensure_tiles(c, (n + kEncTile - 1) / kEncTile);
+        if (st != HUFF_OK) return st;
+        st = launch_hist_only(c, d_in, n, c->tile_hist, s);
         if (st != HUFF_OK) return st;
     }
     CbArgs a;
@@ -367,7 +388,7 @@ huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t
     st = hip_status(launch_codebook(a, s));
     if (st != HUFF_OK) return st;
     return launch_encode_one(c, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
-                             d_status, s);
+                             d_status, true, s);
 }
 
 huff_status huff_decode(huff_ctx* c, const uint32_t* d_words, uint64_t nwords, const uint64_t* d_chunk_off,

@@ -9,21 +9,15 @@
 
 namespace huff {
 
-constexpr int kEncThreads = 512;                 // encode workgroup
-constexpr int kEncUnit = 32;                     // input bytes per encode thread
+constexpr int kEncThreads = 256;                 // encode workgroup
+constexpr int kEncUnit = 64;                     // input bytes per encode thread
 constexpr int kEncTile = kEncThreads * kEncUnit; // 16 KiB per tile
 constexpr int kCbThreads = 256;                  // codebook workgroup (one per file)
 constexpr int kHistThreads = 512;
+constexpr int kScanTilesPerBlock = 1024;         // tiles per k_tile_scan block
 constexpr int kHistMaxDepth = 32;
 constexpr uint32_t kNoSub = 0xFFFFFFFFu;         // sub_log2 when there is no sub index
 constexpr uint64_t kMaxN = 1ull << 38;
-
-// Look-back status word: [63:62] flag, [61:44] epoch, [43:0] bit count.
-constexpr int kEpochBits = 18;
-constexpr uint32_t kEpochMax = (1u << kEpochBits) - 1;
-constexpr uint64_t kValueMask = (1ull << 44) - 1;
-constexpr uint64_t kFlagAgg = 1ull << 62;
-constexpr uint64_t kFlagPre = 2ull << 62;
 
 // Histogram accumulator (device).  Workgroup w adds into copy
 // w % kHistCopies, which spreads same-address atomics; the kernel that
@@ -55,11 +49,19 @@ struct EncArgs {
     uint32_t nfiles;
     uint32_t chunk_log2;
     uint32_t sub_log2;      // kNoSub if no sub index
-    uint32_t epoch;         // tag of this launch's look-back words (1..kEpochMax)
-    const uint32_t* epoch_ptr;  // if set, the tag is read from here instead
-    uint64_t ntiles;        // total over all files (= grid size)
-    unsigned long long* lb; // look-back status words, >= ntiles
+    uint64_t ntiles;        // total over all files
+    const uint32_t* tile_local;            // first bit of each tile inside its scan block
+    const unsigned long long* blk_total;   // code bits of each scan block
     int32_t* err;           // fallback status word
+};
+
+struct ScanArgs {
+    const uint16_t* tile_hist;  // per-tile histograms, or ...
+    const uint32_t* tile_bits;  // ... per-tile bit counts
+    const huff_dcb* cb;
+    uint64_t ntiles;
+    uint32_t* tile_local;
+    unsigned long long* blk_total;
 };
 
 struct DecArgs {
@@ -77,8 +79,9 @@ struct HistArgs {
     const uint8_t* in;
     uint64_t n;
     HistState* st;
+    uint16_t* tile_hist;    // optional per-16 KiB-tile histograms, [ntiles][256]
     uint32_t depth_log2;
-    uint64_t per_block;     // bytes per workgroup (multiple of 16)
+    uint64_t tiles_per_block;
 };
 
 struct CbArgs {
@@ -95,8 +98,9 @@ struct CbArgs {
 hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s);
 hipError_t launch_codebook(const CbArgs& a, hipStream_t s);
-hipError_t launch_encode(const EncArgs& a, hipStream_t s);
-hipError_t launch_epoch_bump(uint32_t* epoch, unsigned long long* lb, uint64_t cap, hipStream_t s);
+hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, uint32_t* tile_bits, hipStream_t s);
+hipError_t launch_tile_scan(const ScanArgs& a, hipStream_t s);
+hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo, hipStream_t s);
 hipError_t launch_decode(const DecArgs& a, uint32_t block, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);

@@ -57,21 +57,46 @@ __device__ __forceinline__ uint32_t find_file(const FileDesc* files, uint32_t nf
 }
 
 // ============================================================== histogram
+__device__ __forceinline__ uint32_t byte32(const uint4& x0, const uint4& x1, int i) {
+    return i < 16 ? byte_of(x0, i) : byte_of(x1, i - 16);
+}
+
+// Unaligned-safe 16-byte load; bytes at or past n read as zero.
+__device__ __forceinline__ uint4 load16(const uint8_t* in, uint64_t q, uint64_t n, bool aligned) {
+    if (aligned && q + 16 <= n) return *reinterpret_cast<const uint4*>(in + q);
+    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const uint32_t b = q + i < n ? (uint32_t)in[q + i] : 0u;
+        const uint32_t sh = 8 * (i & 3);
+        if (i < 4) w0 |= b << sh;
+        else if (i < 8) w1 |= b << sh;
+        else if (i < 12) w2 |= b << sh;
+        else w3 |= b << sh;
+    }
+    return make_uint4(w0, w1, w2, w3);
+}
+
+// Persistent histogram over 16 KiB tiles (the encode tile).  Workgroup b
+// takes a contiguous run of tiles; each thread counts 2 x 16 bytes per tile
+// into LDS replicas laid out [value][replica] (the lanes of a wave hit
+// different banks), with the next tile's loads issued before the current
+// tile is counted.  With a tile_hist buffer the replicas are flushed after
+// every tile into a u16 per-tile histogram (what the encoder's tile offsets
+// are computed from).  Each workgroup adds its totals into accumulator copy
+// b % kHistCopies; the consumer sums and zeroes the copies.
 __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
     __shared__ uint32_t sh[256 * kHistMaxDepth];
     const uint32_t dl = a.depth_log2, depth = 1u << dl;
     const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < 256u * depth; i += blockDim.x) sh[i] = 0;
-    __syncthreads();
+    for (uint32_t i = tid; i < 256u * depth; i += kHistThreads) sh[i] = 0;
     const uint32_t rep = tid & (depth - 1);
     const uint8_t* in = a.in;
     const uint64_t n = a.n;
-    const uint64_t head = min<uint64_t>(n, (16u - ((uintptr_t)in & 15u)) & 15u);
-    const uint64_t nvec = (n - head) >> 4;
-    const uint4* vec = reinterpret_cast<const uint4*>(in + head);
-    const uint64_t per = a.per_block >> 4;
-    const uint64_t vlo = (uint64_t)blockIdx.x * per;
-    const uint64_t vhi = min(nvec, vlo + per);
+    const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
+    const uint64_t t0 = (uint64_t)blockIdx.x * a.tiles_per_block;
+    const uint64_t t1 = min(ntiles, t0 + a.tiles_per_block);
+    const bool aligned = ((uintptr_t)in & 15u) == 0;
     auto count = [&](uint32_t b) { atomicAdd(&sh[(b << dl) | rep], 1u); };
     auto count4 = [&](uint32_t w) {
         count(w & 0xffu);
@@ -79,29 +104,53 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
         count((w >> 16) & 0xffu);
         count(w >> 24);
     };
-    uint64_t i = vlo + tid;
-    const uint32_t stride = blockDim.x;
-    for (; i + 3 * stride < vhi; i += 4 * stride) {
-        uint4 q0 = vec[i], q1 = vec[i + stride], q2 = vec[i + 2 * stride], q3 = vec[i + 3 * stride];
-        count4(q0.x); count4(q0.y); count4(q0.z); count4(q0.w);
-        count4(q1.x); count4(q1.y); count4(q1.z); count4(q1.w);
-        count4(q2.x); count4(q2.y); count4(q2.z); count4(q2.w);
-        count4(q3.x); count4(q3.y); count4(q3.z); count4(q3.w);
-    }
-    for (; i < vhi; i += stride) {
-        uint4 q = vec[i];
-        count4(q.x); count4(q.y); count4(q.z); count4(q.w);
-    }
-    if (blockIdx.x == 0) {
-        for (uint64_t k = tid; k < head; k += stride) count(in[k]);
-        for (uint64_t k = head + (nvec << 4) + tid; k < n; k += stride) count(in[k]);
+    auto count16 = [&](const uint4 q, uint64_t at) {
+        if (at + 16 <= n) {
+            count4(q.x); count4(q.y); count4(q.z); count4(q.w);
+        } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (at + i < n) count(byte_of(q, i));
+        }
+    };
+    unsigned long long total = 0;
+    const uint64_t off = (uint64_t)tid * 16;
+    uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
+    if (t0 < t1) {
+        q0 = load16(in, t0 * kEncTile + off, n, aligned);
+        q1 = load16(in, t0 * kEncTile + kEncTile / 2 + off, n, aligned);
     }
     __syncthreads();
-    for (uint32_t v = tid; v < 256; v += stride) {
-        uint32_t s = 0;
-        for (uint32_t r = 0; r < depth; ++r) s += sh[(v << dl) | ((r + v) & (depth - 1))];
-        if (s) atomicAdd(&a.st->acc[blockIdx.x % kHistCopies][v], (unsigned long long)s);
+    for (uint64_t t = t0; t < t1; ++t) {
+        const uint4 c0 = q0, c1 = q1;
+        const uint64_t base = t * kEncTile;
+        if (t + 1 < t1) {
+            q0 = load16(in, base + kEncTile + off, n, aligned);
+            q1 = load16(in, base + kEncTile + kEncTile / 2 + off, n, aligned);
+        }
+        count16(c0, base + off);
+        count16(c1, base + kEncTile / 2 + off);
+        if (a.tile_hist) {
+            __syncthreads();
+            if (tid < 256) {
+                uint32_t s = 0;
+                for (uint32_t r = 0; r < depth; ++r) {
+                    const uint32_t k = (tid << dl) | ((r + tid) & (depth - 1));
+                    s += sh[k];
+                    sh[k] = 0;
+                }
+                a.tile_hist[t * 256 + tid] = (uint16_t)s;
+                total += s;
+            }
+            __syncthreads();
+        }
     }
+    if (!a.tile_hist) {
+        __syncthreads();
+        if (tid < 256)
+            for (uint32_t r = 0; r < depth; ++r) total += sh[(tid << dl) | ((r + tid) & (depth - 1))];
+    }
+    if (tid < 256 && total) atomicAdd(&a.st->acc[blockIdx.x % kHistCopies][tid], total);
 }
 
 // Sums the accumulator copies into d_hist and zeroes them for the next launch.
@@ -371,13 +420,96 @@ hipError_t launch_codebook(const CbArgs& a, hipStream_t s) {
 }
 
 // ================================================================= encode
-// One workgroup per tile of 16 KiB (512 threads x 32 bytes), tile index =
-// blockIdx.  A tile's first stream bit comes from a decoupled look-back over
-// the earlier tiles' published bit counts.  The wait is bounded: if a
-// predecessor has published nothing after kSpinLimit polls, the waiting wave
-// counts that tile's bits itself and publishes them on its behalf (the same
-// value the owner will publish), so progress never depends on the order in
-// which workgroups are dispatched.  No atomic read-modify-write is used.
+// Tile offsets.  A tile's code bits are known before it is encoded: from its
+// u16 histogram (sum of count x length, written by k_hist) or, for a
+// standalone encode, counted by k_tile_bits.  k_tile_scan turns them into an
+// exclusive prefix inside blocks of kScanTiles tiles plus one total per
+// block, so k_encode never waits on another workgroup.
+constexpr int kScanTiles = kScanTilesPerBlock;
+
+__global__ __launch_bounds__(kEncThreads) void k_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb,
+                                                            uint32_t* tile_bits) {
+    __shared__ uint8_t s_len[256];
+    __shared__ uint32_t s_sum[kEncThreads / 64];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t g = blockIdx.x;
+    s_len[tid] = cb->len[tid];
+    const bool aligned = ((uintptr_t)in & 15u) == 0;
+    const uint64_t q = g * kEncTile + (uint64_t)tid * kEncUnit;
+    uint4 x[kEncUnit / 16];
+#pragma unroll
+    for (int k = 0; k < kEncUnit / 16; ++k) x[k] = load16(in, q + 16 * k, n, aligned);
+    __syncthreads();
+    uint32_t sum = 0;
+    const uint32_t nv = q >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q);
+#pragma unroll
+    for (int i = 0; i < kEncUnit; ++i) sum += (uint32_t)i < nv ? s_len[byte_of(x[i >> 4], i & 15)] : 0u;
+    sum = (uint32_t)wave_sum_u64(sum);
+    if ((tid & 63) == 0) s_sum[tid >> 6] = sum;
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t t = 0;
+        for (int w = 0; w < kEncThreads / 64; ++w) t += s_sum[w];
+        tile_bits[g] = t;
+    }
+}
+
+__global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
+    __shared__ uint32_t s_len[256];
+    __shared__ uint32_t s_wsum[kScanTiles / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 256) s_len[tid] = a.cb->len[tid];
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * kScanTiles + tid;
+    uint32_t bits = 0;
+    if (t < a.ntiles) {
+        if (a.tile_hist) {
+            const uint4* h = reinterpret_cast<const uint4*>(a.tile_hist + t * 256);
+#pragma unroll 4
+            for (int i = 0; i < 32; ++i) {
+                const uint4 c = h[i];
+                const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    bits += (w[k] & 0xffffu) * s_len[8 * i + 2 * k];
+                    bits += (w[k] >> 16) * s_len[8 * i + 2 * k + 1];
+                }
+            }
+        } else {
+            bits = a.tile_bits[t];
+        }
+    }
+    const uint32_t incl = wave_incl_scan(bits);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kScanTiles / 64; ++w) {
+        const uint32_t ws = s_wsum[w];
+        total += ws;
+        before += w < (int)wave ? ws : 0u;
+    }
+    if (t < a.ntiles) a.tile_local[t] = before + incl - bits;
+    if (tid == 0) a.blk_total[blockIdx.x] = total;
+}
+
+hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, uint32_t* tile_bits, hipStream_t s) {
+    const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
+    hipLaunchKernelGGL(k_tile_bits, dim3((uint32_t)ntiles), dim3(kEncThreads), 0, s, in, n, cb, tile_bits);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_scan(const ScanArgs& a, hipStream_t s) {
+    const uint64_t blocks = (a.ntiles + kScanTiles - 1) / kScanTiles;
+    hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)blocks), dim3(kScanTiles), 0, s, a);
+    return hipGetLastError();
+}
+
+// Persistent encode over 16 KiB tiles (256 threads x 64 bytes); workgroup w
+// takes tiles w, w + G, w + 2G, ... and requests the next tile's bytes while
+// it encodes the current one.  Each thread packs its 64 bytes into a private
+// LDS slot with one table lookup per byte; the workgroup scans the
+// per-thread bit counts; the tile's first stream bit is its block prefix
+// plus its offset inside the block.
 //
 // Output words are owned by the thread whose bit range holds the word's last
 // bit; the bits of the owner's first word that precede its range belong to
@@ -385,335 +517,335 @@ hipError_t launch_codebook(const CbArgs& a, hipStream_t s) {
 // thread of a tile, are re-derived from the 32 input bytes before the tile.
 // The final partial word of a stream is written by its last thread.  No two
 // threads write the same word.
-constexpr int kSlotWords = 16;   // private LDS words per thread: 32 bytes x 16 bits
+constexpr int kSlotWords = kEncUnit * 16 / 32 + 1;  // 64 bytes x 16 bits, plus a zero word
+constexpr int kSlotStride = kEncThreads + 1;           // word k of thread t at [k*stride + t]: banks differ along k
 constexpr int kEncWaves = kEncThreads / 64;
-constexpr int kSpinLimit = 64;
 
-__device__ __forceinline__ uint4 load16(const uint8_t* in, uint64_t q, uint64_t n, bool aligned) {
-    if (aligned && q + 16 <= n) return *reinterpret_cast<const uint4*>(in + q);
-    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
-#pragma unroll
-    for (int i = 0; i < 16; ++i) {
-        const uint32_t b = q + i < n ? (uint32_t)in[q + i] : 0u;
-        const uint32_t sh = 8 * (i & 3);
-        if (i < 4) w0 |= b << sh;
-        else if (i < 8) w1 |= b << sh;
-        else if (i < 12) w2 |= b << sh;
-        else w3 |= b << sh;
-    }
-    return make_uint4(w0, w1, w2, w3);
+__device__ __forceinline__ uint32_t byte64(const uint4& a, const uint4& b, const uint4& c, const uint4& d, int i) {
+    return i < 16 ? byte_of(a, i) : i < 32 ? byte_of(b, i - 16) : i < 48 ? byte_of(c, i - 32) : byte_of(d, i - 48);
 }
 
-__device__ __forceinline__ uint32_t byte32(const uint4& x0, const uint4& x1, int i) {
-    return i < 16 ? byte_of(x0, i) : byte_of(x1, i - 16);
-}
-
-// Bits of a whole (full) tile, counted by one wave.
-__device__ uint32_t wave_tile_bits(const uint8_t* in, uint64_t tstart, bool aligned, const uint8_t* s_len) {
-    uint32_t sum = 0;
-    const int lane = __lane_id();
-    for (int v = 0; v < kEncTile / (64 * 16); ++v) {
-        const uint4 x = load16(in, tstart + (uint64_t)(v * 64 + lane) * 16, ~0ull, aligned);
+// Packs one thread's 64 bytes (codes of at most 16 bits) into its LDS slot,
+// left-aligned and followed by a zero word: G codes at a time are joined
+// into one 32-bit group (so G codes of at most 32/G bits) before the group is
+// appended to a 64-bit accumulator.  Every group stores the accumulator's
+// current top word and moves to the next slot word only once that word is
+// full, so there is no branch.  G = 4 reads 8-bit codes from a byte table
+// indexed by the input byte itself.  G = 1 handles a partial unit of nv bytes.
+template <int G>
+__device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const uint4 x2, const uint4 x3,
+                                          const uint8_t* s_len, const uint8_t* s_code8, const uint16_t* s_code16,
+                                          uint32_t* slot, uint32_t& L, uint32_t& nwp, uint32_t& bad,
+                                          uint32_t nv = kEncUnit) {
+    uint64_t acc = 0;
+    uint32_t na = 0, wi = 0;
+    auto emit = [&]() {
+        const uint32_t sh = na >= 32 ? na - 32 : 0;
+        slot[wi * kSlotStride] = (uint32_t)(acc >> sh);
+        const uint32_t full = na >= 32 ? 1u : 0u;
+        wi += full;
+        na -= full << 5;
+    };
+    if constexpr (G == 1) {
+        for (uint32_t i = 0; i < nv; ++i) {
+            const uint32_t v = byte64(x0, x1, x2, x3, (int)i);
+            const uint32_t l = s_len[v];
+            bad |= l == 0;
+            acc = (acc << l) | s_code16[v];
+            na += l;
+            emit();
+        }
+    } else {
 #pragma unroll
-        for (int i = 0; i < 16; ++i) sum += s_len[byte_of(x, i)];
+        for (int i0 = 0; i0 < kEncUnit; i0 += G) {
+            uint32_t g = 0, gl = 0;
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                if (i0 + k < kEncUnit) {
+                    const uint32_t v = byte64(x0, x1, x2, x3, i0 + k);
+                    const uint32_t l = s_len[v];
+                    const uint32_t c = G == 4 ? (uint32_t)s_code8[v] : (uint32_t)s_code16[v];
+                    bad |= l == 0 ? 1u : 0u;
+                    g = (g << l) | c;
+                    gl += l;
+                }
+            }
+            acc = (acc << gl) | g;
+            na += gl;
+            emit();
+        }
     }
-    return (uint32_t)wave_sum_u64(sum);
+    L = wi * 32 + na;
+    nwp = wi;
+    if (na) {
+        slot[wi * kSlotStride] = (uint32_t)(acc << (32 - na));
+        ++nwp;
+    }
+    slot[nwp * kSlotStride] = 0;
 }
 
 template <bool kBatch>
 __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
-    __shared__ uint32_t s_slot[kSlotWords * kEncThreads];  // word k of thread t at [k*T + t]; tile bytes (generic)
-    __shared__ uint32_t s_enc[256];
+    __shared__ uint32_t s_slot[kSlotWords * kSlotStride];  // private slots; tile bytes (generic path)
     __shared__ unsigned long long s_code[256];
+    __shared__ uint16_t s_code16[256];
+    __shared__ uint8_t s_code8[256];
     __shared__ uint8_t s_len[256];
     __shared__ uint8_t s_prev[32];
     __shared__ uint32_t s_L[kEncThreads];
     __shared__ uint32_t s_wsum[kEncWaves];
-    __shared__ unsigned long long s_lbp[kEncWaves], s_lbi[kEncWaves], s_lsum[kEncWaves];
-    __shared__ unsigned long long s_excl;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint64_t g = blockIdx.x;
-    FileDesc f;
-    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, g)];
-    else f = a.one;
-    const uint32_t epoch = a.epoch_ptr ? *a.epoch_ptr : a.epoch;
-    const uint64_t tagE = (uint64_t)epoch << 44;
-    const uint64_t j = g - f.first;
-    const uint64_t n = f.n;
-    const uint64_t tstart = j * (uint64_t)kEncTile;
-    const uint64_t q0 = tstart + (uint64_t)tid * kEncUnit;
-    const uint32_t nv = q0 >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q0);
-    const bool aligned = ((uintptr_t)f.in & 15u) == 0;
-    const uint4 x0 = load16(f.in, q0, n, aligned);
-    const uint4 x1 = load16(f.in, q0 + 16, n, aligned);
-    if (tid < 32 && j > 0) s_prev[tid] = f.in[tstart - 32 + tid];
-    const uint32_t maxLen = f.cb->max_len;
-    const bool fast = maxLen <= 16;
-    if (tid < 256) {
-        s_len[tid] = f.cb->len[tid];
-        if (fast) s_enc[tid] = f.cb->enc[tid];
-        else s_code[tid] = f.cb->code[tid];
-    }
-    __syncthreads();
+    const huff_dcb* loaded = nullptr;
+    bool fast = true;
+    uint32_t group = 1;
+    uint64_t blkDone = 0;           // scan blocks already summed into blkPrefix
+    unsigned long long blkPrefix = 0;
 
-    // 1) pack into the private slot (fast) or count bits (generic)
-    uint32_t L = 0, mid = 0, nwp = 0;
-    bool missing = false;
-    if (fast) {
-        uint64_t acc = 0;
-        uint32_t na = 0, wi = 0;
-        auto put = [&](uint32_t e) {
-            const uint32_t len = e & 0xffu;
-            missing |= len == 0;
-            acc = (acc << len) | (e >> 8);
-            na += len;
-            if (na >= 32) {
-                na -= 32;
-                s_slot[wi * kEncThreads + tid] = (uint32_t)(acc >> na);
-                ++wi;
-            }
-        };
-        if (nv == kEncUnit) {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) put(s_enc[byte_of(x0, i)]);
-            mid = wi * 32 + na;
-#pragma unroll
-            for (int i = 0; i < 16; ++i) put(s_enc[byte_of(x1, i)]);
-        } else {
-            for (uint32_t i = 0; i < nv; ++i) {
-                put(s_enc[byte32(x0, x1, (int)i)]);
-                if (i == 15) mid = wi * 32 + na;
-            }
+    auto fileOf = [&](uint64_t tile) -> const FileDesc& {
+        if constexpr (kBatch) return a.files[find_file(a.files, a.nfiles, tile)];
+        else return a.one;
+    };
+    auto loadUnit = [&](uint64_t tile, uint4& y0, uint4& y1, uint4& y2, uint4& y3) {
+        const FileDesc& d = fileOf(tile);
+        const uint64_t q = (tile - d.first) * (uint64_t)kEncTile + (uint64_t)tid * kEncUnit;
+        const bool al = ((uintptr_t)d.in & 15u) == 0;
+        y0 = load16(d.in, q, d.n, al);
+        y1 = load16(d.in, q + 16, d.n, al);
+        y2 = load16(d.in, q + 32, d.n, al);
+        y3 = load16(d.in, q + 48, d.n, al);
+    };
+    // A tile's first stream bit = sum of the block totals before its scan
+    // block + its offset inside the block.  Both are fetched one tile ahead
+    // with vector loads: a scalar load would share its wait counter with the
+    // LDS table lookups and stall them for a memory round trip.
+    auto tileStart = [&](uint64_t tile, uint64_t& done, unsigned long long& prefix) -> uint64_t {
+        const FileDesc& d = fileOf(tile);
+        const uint64_t blk = tile / kScanTiles;
+        if (kBatch) {
+            const uint64_t fb = d.first / kScanTiles;  // files start at scan-block boundaries
+            if (done < fb || done > blk) { done = fb; prefix = 0; }
         }
-        L = wi * 32 + na;
-        nwp = wi;
-        if (na) {
-            s_slot[wi * kEncThreads + tid] = (uint32_t)(acc << (32 - na));
-            ++nwp;
-        }
-    } else {
-        reinterpret_cast<uint4*>(s_slot)[2 * tid] = x0;
-        reinterpret_cast<uint4*>(s_slot)[2 * tid + 1] = x1;
-        for (uint32_t i = 0; i < nv; ++i) {
-            const uint32_t l = s_len[byte32(x0, x1, (int)i)];
-            missing |= l == 0;
-            L += l;
-            if (i == 15) mid = L;
-        }
+        uint32_t lane0 = (uint32_t)(tid >> 10);  // 0, but not known to the compiler: forces vector loads
+        asm volatile("" : "+v"(lane0));
+        for (; done < blk; ++done) prefix += a.blk_total[done + lane0];
+        return prefix + a.tile_local[tile + lane0];
+    };
+    uint64_t g = blockIdx.x;
+    uint4 x0 = make_uint4(0, 0, 0, 0), x1 = x0, x2 = x0, x3 = x0;
+    uint64_t Scur = 0;
+    if (g < a.ntiles) {
+        loadUnit(g, x0, x1, x2, x3);
+        Scur = tileStart(g, blkDone, blkPrefix);
     }
-    if (missing) report(f.status, a.err, HUFF_E_INVAL);
-
-    // 2) workgroup exclusive scan of per-thread bit counts
-    s_L[tid] = L;
-    const uint32_t incl = wave_incl_scan(L);
-    if (lane == 63) s_wsum[wave] = incl;
-    __syncthreads();
-    uint32_t before = 0, agg = 0;
-#pragma unroll
-    for (int w = 0; w < kEncWaves; ++w) {
-        const uint32_t ws = s_wsum[w];
-        agg += ws;
-        before += w < wave ? ws : 0u;
-    }
-    const uint32_t excl = before + incl - L;
-
-    // 3) decoupled look-back for the tile's first stream bit.  The whole
-    //    workgroup reads kEncThreads predecessors per round trip.
-    unsigned long long* lb = a.lb + (g - j);  // this file's look-back words
-    if (j == 0) {
-        if (tid == 0) {
-            __hip_atomic_store(&lb[0], kFlagPre | tagE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_excl = 0;
+    for (; g < a.ntiles; g += gridDim.x) {
+        const FileDesc& f = fileOf(g);
+        const uint64_t j = g - f.first;
+        const uint64_t n = f.n;
+        const uint64_t tstart = j * (uint64_t)kEncTile;
+        const uint64_t q0 = tstart + (uint64_t)tid * kEncUnit;
+        const uint32_t nv = q0 >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q0);
+        // the next tile's bytes are requested now and used next iteration
+        const uint64_t gn = g + gridDim.x;
+        uint4 y0 = make_uint4(0, 0, 0, 0), y1 = y0, y2 = y0, y3 = y0;
+        uint64_t Snext = 0;
+        if (gn < a.ntiles) {
+            loadUnit(gn, y0, y1, y2, y3);
+            Snext = tileStart(gn, blkDone, blkPrefix);
         }
-    } else {
-        if (tid == 0)
-            __hip_atomic_store(&lb[j], kFlagAgg | tagE | (uint64_t)agg, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        uint64_t sum = 0;
-        int64_t pos = (int64_t)j - 1;
-        int spins = 0;
-        for (;;) {
-            const int64_t idx = pos - tid;
-            uint64_t st = 0;
-            bool valid = true, pre = true;
-            if (idx >= 0) {
-                st = __hip_atomic_load(&lb[idx], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t fl = (uint32_t)(st >> 62);
-                valid = fl != 0 && (uint32_t)((st >> 44) & kEpochMax) == epoch;
-                pre = valid && fl == 2;
+        __syncthreads();  // the previous tile is done with the LDS slots and tables
+        if (tid < 32 && j > 0) s_prev[tid] = f.in[tstart - 32 + tid];
+        if (f.cb != loaded) {
+            const uint32_t maxLen = f.cb->max_len;
+            fast = maxLen <= 16;
+            group = maxLen <= 8 ? 4 : maxLen <= 10 ? 3 : 2;  // codes per 32-bit group
+            {
+                const uint64_t c = f.cb->code[tid];
+                s_len[tid] = f.cb->len[tid];
+                s_code[tid] = c;
+                s_code16[tid] = (uint16_t)c;
+                s_code8[tid] = (uint8_t)c;
             }
-            const uint64_t bp = __ballot(pre), bi = __ballot(!valid);
-            if (lane == 0) {
-                s_lbp[wave] = bp;
-                s_lbi[wave] = bi;
-            }
+            loaded = f.cb;
             __syncthreads();
-            // nearest prefix-carrying predecessor (lowest thread index), and
-            // whether every predecessor up to it has published
-            int first = kEncThreads;
-            bool waitMore = false;
-#pragma unroll
-            for (int w = 0; w < kEncWaves; ++w) {
-                const uint64_t p = s_lbp[w], iv = s_lbi[w];
-                if (first == kEncThreads) {
-                    const uint64_t upto = p ? ((p & (~p + 1)) << 1) - 1 : ~0ull;  // bits up to the lowest set one
-                    if (iv & upto) waitMore = true;
-                    if (p) first = 64 * w + __ffsll((unsigned long long)p) - 1;
+        }
+        const uint64_t S = Scur;  // the tile's first stream bit
+
+        // 1) pack into the private slot (fast) or count bits (generic)
+        uint32_t L = 0, nwp = 0, bad = 0;
+        if (fast) {
+            uint32_t* slot = s_slot + tid;  // stride kSlotStride
+            if (nv == kEncUnit) {
+                // opaque copies keep the variants from sharing (and hoisting)
+                // their byte extraction and table reads
+                uint4 z0 = x0, z1 = x1, z2 = x2, z3 = x3;
+                asm volatile("" : "+v"(z0.x), "+v"(z0.y), "+v"(z0.z), "+v"(z0.w), "+v"(z1.x), "+v"(z1.y), "+v"(z1.z), "+v"(z1.w)::"memory");
+                asm volatile("" : "+v"(z2.x), "+v"(z2.y), "+v"(z2.z), "+v"(z2.w), "+v"(z3.x), "+v"(z3.y), "+v"(z3.z), "+v"(z3.w)::"memory");
+                if (group == 4) {
+                    pack_unit<4>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp, bad);
+                } else if (group == 3) {
+                    asm volatile("" : "+v"(z0.x), "+v"(z1.x), "+v"(z2.x), "+v"(z3.x)::"memory");
+                    pack_unit<3>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp, bad);
+                } else {
+                    asm volatile("" : "+v"(z0.y), "+v"(z1.y), "+v"(z2.y), "+v"(z3.y)::"memory");
+                    pack_unit<2>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp, bad);
                 }
+            } else {
+                pack_unit<1>(x0, x1, x2, x3, s_len, s_code8, s_code16, slot, L, nwp, bad, nv);
             }
-            if (waitMore) {
-                __syncthreads();
-                if (++spins < kSpinLimit) {
-                    __builtin_amdgcn_s_sleep(2);
-                    continue;
-                }
-                // count the nearest silent predecessor's bits ourselves and
-                // publish them on its behalf
-                int z = kEncThreads;
+        } else {
+            uint4* in4 = reinterpret_cast<uint4*>(s_slot) + 4 * tid;
+            in4[0] = x0;
+            in4[1] = x1;
+            in4[2] = x2;
+            in4[3] = x3;
+            for (uint32_t i = 0; i < nv; ++i) {
+                const uint32_t l = s_len[byte64(x0, x1, x2, x3, (int)i)];
+                bad |= l == 0;
+                L += l;
+            }
+        }
+        if (bad) report(f.status, a.err, HUFF_E_INVAL);
+
+        // 2) workgroup exclusive scan of per-thread bit counts
+        s_L[tid] = L;
+        const uint32_t incl = wave_incl_scan(L);
+        if (lane == 63) s_wsum[wave] = incl;
+        __syncthreads();
+        uint32_t before = 0, agg = 0;
 #pragma unroll
-                for (int w = kEncWaves - 1; w >= 0; --w)
-                    if (s_lbi[w]) z = 64 * w + __ffsll((unsigned long long)s_lbi[w]) - 1;
-                const uint64_t tz = (uint64_t)(pos - z);
-                if (wave == 0) {
-                    const uint32_t bits = wave_tile_bits(f.in, tz * kEncTile, aligned, s_len);
-                    if (lane == 0) {
-                        const uint64_t cur = __hip_atomic_load(&lb[tz], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        const bool curValid = (cur >> 62) != 0 && (uint32_t)((cur >> 44) & kEpochMax) == epoch;
-                        if (!curValid)
-                            __hip_atomic_store(&lb[tz], kFlagAgg | tagE | (uint64_t)bits, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_AGENT);
+        for (int w = 0; w < kEncWaves; ++w) {
+            const uint32_t ws = s_wsum[w];
+            agg += ws;
+            before += w < wave ? ws : 0u;
+        }
+        const uint64_t b = S + before + incl - L, e = b + L;
+        const uint32_t sh = (uint32_t)(b & 31);
+        const bool lastThread = nv > 0 && q0 + kEncUnit >= n;
+
+        // 3) segment index and decode index
+        if (nv) {
+            if ((q0 & ((1ull << a.chunk_log2) - 1)) == 0) f.chunk_off[q0 >> a.chunk_log2] = b;
+            if (a.sub_log2 != kNoSub) {
+                if (a.sub_log2 >= 6) {
+                    if ((q0 & ((1ull << a.sub_log2) - 1)) == 0) f.sub_lo[q0 >> a.sub_log2] = (uint32_t)b;
+                } else {
+                    // sub-blocks of 16 or 32 bytes: bit offsets inside the unit
+                    const uint32_t step = 1u << a.sub_log2;
+                    uint32_t run = 0;
+                    for (uint32_t at = 0; at < nv; at += step) {
+                        f.sub_lo[(q0 + at) >> a.sub_log2] = (uint32_t)(b + run);
+                        for (uint32_t i = at; i < at + step && i < nv; ++i) run += s_len[byte64(x0, x1, x2, x3, (int)i)];
                     }
                 }
-                __syncthreads();
-                spins = 0;
-                continue;
             }
-            const uint64_t part = wave_sum_u64((tid <= first && idx >= 0) ? (st & kValueMask) : 0ull);
-            if (lane == 0) s_lsum[wave] = part;
-            __syncthreads();
-#pragma unroll
-            for (int w = 0; w < kEncWaves; ++w) sum += s_lsum[w];
-            __syncthreads();
-            if (first < kEncThreads) break;
-            pos -= kEncThreads;
         }
-        if (tid == 0) {
-            __hip_atomic_store(&lb[j], kFlagPre | tagE | (sum + agg), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_excl = sum;
+        if (lastThread) {
+            f.chunk_off[(n + (1ull << a.chunk_log2) - 1) >> a.chunk_log2] = e;
+            if (a.sub_log2 != kNoSub) f.sub_lo[(n + (1ull << a.sub_log2) - 1) >> a.sub_log2] = (uint32_t)e;
+            if (((e + 31) >> 5) > f.nwords) report(f.status, a.err, HUFF_E_CAPACITY);
         }
-    }
-    __syncthreads();
-    const uint64_t S = s_excl;
-    const uint64_t b = S + excl, e = b + L;
-    const uint32_t sh = (uint32_t)(b & 31);
-    const bool lastThread = nv > 0 && q0 + kEncUnit >= n;
 
-    // 4) segment index and decode index
-    if (nv) {
-        if ((q0 & ((1ull << a.chunk_log2) - 1)) == 0) f.chunk_off[q0 >> a.chunk_log2] = b;
-        if (a.sub_log2 != kNoSub) {
-            if ((q0 & ((1ull << a.sub_log2) - 1)) == 0) f.sub_lo[q0 >> a.sub_log2] = (uint32_t)b;
-            if (a.sub_log2 == 4 && nv > 16) f.sub_lo[(q0 >> 4) + 1] = (uint32_t)(b + mid);
-        }
-    }
-    if (lastThread) {
-        f.chunk_off[(n + (1ull << a.chunk_log2) - 1) >> a.chunk_log2] = e;
-        if (a.sub_log2 != kNoSub) f.sub_lo[(n + (1ull << a.sub_log2) - 1) >> a.sub_log2] = (uint32_t)e;
-        if (((e + 31) >> 5) > f.nwords) report(f.status, a.err, HUFF_E_CAPACITY);
-    }
-
-    // 5) the bits before b that share b's word, right-aligned
-    uint32_t prefix = 0;
-    if (sh && nv) {
-        if (tid > 0 && fast && s_L[tid - 1] >= sh) {
-            const uint32_t Lp = s_L[tid - 1];
-            const uint32_t q = Lp - sh, i = q >> 5, o = q & 31;
-            const uint32_t nwprev = (Lp + 31) >> 5;
-            const uint64_t hi = s_slot[i * kEncThreads + tid - 1];
-            const uint64_t lo = i + 1 < nwprev ? s_slot[(i + 1) * kEncThreads + tid - 1] : 0u;
-            prefix = (uint32_t)((((hi << 32) | lo) << o) >> 32) >> (32 - sh);
-        } else {
-            // re-derive from the bytes just before this thread's unit
-            uint64_t acc = 0;
-            uint32_t nb = 0;
-            for (int k = 31; k >= 0 && nb < sh; --k) {
-                const uint32_t v = tid == 0 ? s_prev[k] : reinterpret_cast<const uint8_t*>(s_slot)[(tid - 1) * kEncUnit + k];
-                const uint64_t c = fast ? (uint64_t)(s_enc[v] >> 8) : s_code[v];
-                acc |= c << nb;
-                nb += s_len[v];
-            }
-            prefix = (uint32_t)acc & ((1u << sh) - 1);
-        }
-    }
-
-    // 6) write the owned words
-    const uint64_t w0 = b >> 5;
-    if (fast) {
-        uint32_t nw = (uint32_t)((e >> 5) - w0);
-        if (lastThread && (e & 31)) ++nw;
-        uint32_t prevw = prefix;
-        for (uint32_t k = 0; k < nw; ++k) {
-            const uint32_t cur = k < nwp ? s_slot[k * kEncThreads + tid] : 0u;
-            const uint32_t v = __builtin_amdgcn_alignbit(prevw, cur, sh);
-            if (w0 + k < f.nwords) f.words[w0 + k] = v;
-            prevw = cur;
-        }
-    } else if (nv) {
-        uint64_t acc = prefix;
-        uint32_t na = sh;
-        uint64_t w = w0;
-        auto put = [&](uint64_t c, uint32_t len) {
-            acc = (acc << len) | c;
-            na += len;
-            if (na >= 32) {
-                na -= 32;
-                if (w < f.nwords) f.words[w] = (uint32_t)(acc >> na);
-                ++w;
-            }
-        };
-        for (uint32_t i = 0; i < nv; ++i) {
-            const uint32_t v = byte32(x0, x1, (int)i);
-            const uint32_t l = s_len[v];
-            const uint64_t c = s_code[v];
-            if (l > 32) {
-                put(c >> 32, l - 32);
-                put(c & 0xffffffffull, 32);
+        // 4) the bits before b that share b's word, right-aligned
+        uint32_t prefix = 0;
+        if (sh && nv) {
+            if (tid > 0 && fast && s_L[tid - 1] >= sh) {
+                const uint32_t Lp = s_L[tid - 1];
+                const uint32_t q = Lp - sh, i = q >> 5, o = q & 31;
+                const uint64_t hi = s_slot[i * kSlotStride + tid - 1];
+                const uint64_t lo = s_slot[(i + 1) * kSlotStride + tid - 1];  // zero past the last word
+                prefix = (uint32_t)((((hi << 32) | lo) << o) >> 32) >> (32 - sh);
             } else {
-                put(c, l);
+                // re-derive from the bytes just before this thread's unit
+                uint64_t acc = 0;
+                uint32_t nb = 0;
+                for (int k = 31; k >= 0 && nb < sh; --k) {
+                    const uint32_t v = tid == 0 ? s_prev[k]
+                                                : reinterpret_cast<const uint8_t*>(s_slot)[(tid - 1) * kEncUnit + 32 + k];
+                    acc |= s_code[v] << nb;
+                    nb += s_len[v];
+                }
+                prefix = (uint32_t)acc & ((1u << sh) - 1);
             }
         }
-        if (lastThread && na && w < f.nwords) f.words[w] = (uint32_t)(acc << (32 - na));
+
+        // 5) write the owned words
+        const uint64_t w0 = b >> 5;
+        const uint64_t tileEnd = S + agg;
+        const bool tileLast = tstart + kEncTile >= n;
+        const bool capOK = ((tileEnd + 31) >> 5) <= f.nwords;  // the whole tile fits
+        if (fast) {
+            uint32_t nw = (uint32_t)((e >> 5) - w0);
+            if (lastThread && (e & 31)) ++nw;
+            uint32_t* wp = f.words + w0;
+            const uint32_t* slot = s_slot + tid;
+            uint32_t prevw = prefix;
+            if (capOK) {
+                // single words up to a 16-byte boundary, then 16-byte stores
+                uint32_t k = 0;
+                const uint32_t head = min(nw, ((uint32_t)(0u - (uint32_t)(uintptr_t)wp) & 15u) >> 2);
+                for (; k < head; ++k) {
+                    const uint32_t cur = slot[k * kSlotStride];
+                    wp[k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
+                    prevw = cur;
+                }
+                for (; k + 4 <= nw; k += 4) {
+                    const uint32_t c0 = slot[k * kSlotStride], c1 = slot[(k + 1) * kSlotStride];
+                    const uint32_t c2 = slot[(k + 2) * kSlotStride], c3 = slot[(k + 3) * kSlotStride];
+                    *reinterpret_cast<uint4*>(wp + k) =
+                        make_uint4(__builtin_amdgcn_alignbit(prevw, c0, sh), __builtin_amdgcn_alignbit(c0, c1, sh),
+                                   __builtin_amdgcn_alignbit(c1, c2, sh), __builtin_amdgcn_alignbit(c2, c3, sh));
+                    prevw = c3;
+                }
+                for (; k < nw; ++k) {
+                    const uint32_t cur = slot[k * kSlotStride];
+                    wp[k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
+                    prevw = cur;
+                }
+            } else {
+                for (uint32_t k = 0; k < nw; ++k) {
+                    const uint32_t cur = slot[k * kSlotStride];
+                    if (w0 + k < f.nwords) wp[k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
+                    prevw = cur;
+                }
+            }
+        } else if (nv) {
+            uint64_t acc = prefix;
+            uint32_t na = sh;
+            uint64_t w = w0;
+            auto put = [&](uint64_t c, uint32_t len) {
+                acc = (acc << len) | c;
+                na += len;
+                if (na >= 32) {
+                    na -= 32;
+                    if (w < f.nwords) f.words[w] = (uint32_t)(acc >> na);
+                    ++w;
+                }
+            };
+            for (uint32_t i = 0; i < nv; ++i) {
+                const uint32_t v = byte64(x0, x1, x2, x3, (int)i);
+                const uint32_t l = s_len[v];
+                const uint64_t c = s_code[v];
+                if (l > 32) {
+                    put(c >> 32, l - 32);
+                    put(c & 0xffffffffull, 32);
+                } else {
+                    put(c, l);
+                }
+            }
+            if (lastThread && na && w < f.nwords) f.words[w] = (uint32_t)(acc << (32 - na));
+        }
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+        Scur = Snext;
     }
 }
 
-hipError_t launch_encode(const EncArgs& a, hipStream_t s) {
-    if (a.files) hipLaunchKernelGGL(k_encode<true>, dim3((uint32_t)a.ntiles), dim3(kEncThreads), 0, s, a);
-    else hipLaunchKernelGGL(k_encode<false>, dim3((uint32_t)a.ntiles), dim3(kEncThreads), 0, s, a);
-    return hipGetLastError();
-}
-
-// Advances a device-side epoch word (for launches replayed from a graph,
-// whose kernel arguments cannot change); clears the look-back words when the
-// epoch wraps.
-__global__ void k_epoch_bump(uint32_t* epoch, unsigned long long* lb, uint64_t cap) {
-    __shared__ uint32_t s_next;
-    if (threadIdx.x == 0) {
-        uint32_t e = *epoch + 1;
-        if (e > kEpochMax || e == 0) e = 0;
-        s_next = e;
-    }
-    __syncthreads();
-    if (s_next == 0) {
-        for (uint64_t i = threadIdx.x; i < cap; i += blockDim.x) lb[i] = 0;
-        __syncthreads();
-        if (threadIdx.x == 0) *epoch = 1;
-    } else if (threadIdx.x == 0) {
-        *epoch = s_next;
-    }
-}
-
-hipError_t launch_epoch_bump(uint32_t* epoch, unsigned long long* lb, uint64_t cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_epoch_bump, dim3(1), dim3(1024), 0, s, epoch, lb, cap);
+hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s) {
+    if (a.files) hipLaunchKernelGGL(k_encode<true>, dim3(grid), dim3(kEncThreads), 0, s, a);
+    else hipLaunchKernelGGL(k_encode<false>, dim3(grid), dim3(kEncThreads), 0, s, a);
     return hipGetLastError();
 }
 

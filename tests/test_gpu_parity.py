@@ -227,12 +227,12 @@ def test_encode_decode_parity(codec, kind, n, chunk, sub):
     _roundtrip(codec, _data(kind, n), chunk, sub)
 
 
-@pytest.mark.parametrize("hist", [(1, 1), (7, 4), (512, 32)])
+@pytest.mark.parametrize("hist", [(1, 1, 1), (7, 4, 3), (512, 32, 16)])
 @pytest.mark.parametrize("dec_block", [64, 256])
 @pytest.mark.parametrize("sub", [0, 16, 32, 64, 128, 256, 512])
 def test_launch_shapes_same_output(P, hist, dec_block, sub):
-    _say(f"launch shapes hist={hist} dec_block={dec_block} sub={sub}")
-    c = P.Codec(0, dict(hist_blocks=hist[0], hist_depth=hist[1], dec_block=dec_block))
+    _say(f"launch shapes hist/enc={hist} dec_block={dec_block} sub={sub}")
+    c = P.Codec(0, dict(hist_blocks=hist[0], hist_depth=hist[1], enc_blocks_per_cu=hist[2], dec_block=dec_block))
     _roundtrip(c, _data("markov", 333_333, seed=hist[0]), 2048, sub)
     c.close()
 
