@@ -72,6 +72,156 @@ def cpu_baseline(a, chunk: int, passes: int):
     return r, out, dt
 
 
+def batch_leg(P, codec, nfiles: int, reps: int):
+    """Many files, one codebook each: the batched path (one graph replay per
+    operation) against a per-file loop of plain calls with a host sync per
+    file, on the same files and buffers."""
+    import numpy as np
+    import torch
+
+    import datagen
+
+    t0 = time.perf_counter()
+    data = [datagen.batch_file(5, i) for i in range(nfiles)]
+    total = sum(a.size for a in data)
+    xs = [torch.from_numpy(a).cuda() for a in data]
+    chunk, sub = 256 << 10, 256
+    files = P.batch_buffers(codec, xs, chunk, sub, bits_per_byte=8)  # byte codes average at most 8 bits
+    gen_s = time.perf_counter() - t0
+    b = P.Batch(codec, files, chunk, sub)
+    b.compress(graph=True)
+    b.decode(graph=True)
+    torch.cuda.synchronize()
+    ok = all(int(f["status"].item()) == 0 for f in files) and all(torch.equal(f["out"], x) for f, x in zip(files, xs))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tc, td = [], []
+    for _ in range(reps):
+        ev[0].record()
+        b.compress(graph=True)
+        ev[1].record()
+        b.decode(graph=True)
+        ev[2].record()
+        torch.cuda.synchronize()
+        tc.append(ev[0].elapsed_time(ev[1]))
+        td.append(ev[1].elapsed_time(ev[2]))
+    # baseline: per-file plain calls, host sync per file
+    loop = []
+    for _ in range(max(1, reps // 5)):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for f in files:
+            c = codec.compress(f["in"], chunk, sub, out=dict(hist=f["hist"], dcb=f["cb"], words=f["words"],
+                                                            chunk_off=f["chunk_off"], sub_lo=f["sub_lo"]))
+            codec.decompress(c, out=f["out"])
+            torch.cuda.synchronize()
+        loop.append(time.perf_counter() - t)
+    ok = ok and all(torch.equal(f["out"], x) for f, x in zip(files, xs))
+    b.close()
+    ms = float(np.median(tc)) + float(np.median(td))
+    loop_s = float(np.median(loop))
+    return {"workload": f"{nfiles} files, sizes log-uniform 4 KiB-16 MiB, i.i.d. Zipf(s~U[0.6,1.6]) over K~U{{16..256}} "
+                        f"bytes each, one codebook per file, C={chunk}, S={sub}",
+            "n_files": nfiles, "n_bytes": total, "compress_ms": round(float(np.median(tc)), 3),
+            "decode_ms": round(float(np.median(td)), 3), "GBps": round(total / (ms * 1e-3) / 1e9, 2),
+            "per_file_loop_GBps": round(total / loop_s / 1e9, 2), "speedup_vs_loop": round(loop_s * 1e3 / ms, 2),
+            "graph": True, "roundtrip_ok": bool(ok), "datagen_s": round(gen_s, 1)}
+
+
+def _dev_equal(pa: int, pb: int, nbytes: int) -> bool:
+    """Compares two device byte ranges (copies both to the host)."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    a, b = np.empty(nbytes, np.uint8), np.empty(nbytes, np.uint8)
+    torch.cuda.synchronize()
+    if nbytes and (hip.hipMemcpy(a.ctypes.data, pa, nbytes, 2) or hip.hipMemcpy(b.ctypes.data, pb, nbytes, 2)):
+        return False
+    return bool(np.array_equal(a, b))
+
+
+def serve_leg(P, seconds: float, pool_n: int, rates):
+    """Open-loop serving: Poisson arrivals at fractions of the saturation
+    rate, 70 % compress / 30 % decompress of resident streams, request sizes
+    log-uniform 1 KiB-64 MiB (Markov text), admission by a 64 GB budget."""
+    import numpy as np
+    import torch
+
+    import datagen
+
+    sizes = [datagen.file_params(6, i, size_lo=1 << 10, size_hi=64 << 20)[0] for i in range(pool_n)]
+    pool = [torch.from_numpy(datagen.markov(n, 6_000_000 + i)).cuda() for i, n in enumerate(sizes)]
+    mean = float(np.mean(sizes))
+    srv = P.Server(mem_budget=64 << 30, nslots=2, max_batch=256, chunk_size=256 << 10, sub_size=256)
+    base = [srv.wait(srv.submit_compress(x)) for x in pool]
+    ref = {i: srv.stream(r["handle"]) for i, r in enumerate(base)}
+    rng = np.random.default_rng(6)
+
+    def make(count, rate):
+        reqs, arr, idx, t = [], [], [], 0.0
+        for _ in range(count):
+            k = int(rng.integers(0, pool_n))
+            if rng.random() < 0.7:
+                reqs.append((0, pool[k], 0))
+            else:
+                reqs.append((2, None, base[k]["handle"]))
+            idx.append(k)
+            arr.append(t)
+            t += float(rng.exponential(1.0 / rate)) if rate else 0.0
+        return reqs, arr, idx
+
+    def run(reqs, arr, keep=()):
+        res = srv.replay(reqs, arr, discard=[j for j in range(len(reqs)) if j not in keep])
+        lat = np.array([r["t_done"] - r["t_submit"] for r in res])
+        t_first = min(r["t_submit"] for r in res)
+        t_last = max(r["t_done"] for r in res)
+        moved = sum((r["in_bytes"] if op == 0 else r["out_bytes"]) for (op, _, _), r in zip(reqs, res))
+        good = all(r["status"] == 0 for r in res)
+        return res, lat, moved / (t_last - t_first) / 1e9, good
+
+    def check_and_release(reqs, idx, res, sample):
+        ok = True
+        for j, ((op, x, h), k, r) in enumerate(zip(reqs, idx, res)):
+            if j not in sample or r["status"] != 0:
+                continue
+            a = srv.stream(r["handle"])
+            if op == 0:  # the served stream equals the one served alone, word for word
+                bref = ref[k]
+                nw = (bref["total_bits"] + 31) // 32
+                ok = ok and a["total_bits"] == bref["total_bits"] and _dev_equal(a["words"], bref["words"], nw * 4)
+            else:  # the decoded bytes equal the pool input
+                ok = ok and _dev_equal(a["out"], pool[k].data_ptr(), pool[k].numel())
+            srv.release(r["handle"])
+        return ok
+
+    # saturation: the whole burst at t = 0
+    reqs, arr, idx = make(min(2000, 8 * pool_n), 0)
+    res, lat, thr, good = run(reqs, arr)
+    lam_sat = thr * 1e9 / mean
+    out = {"workload": f"pool of {pool_n} Markov-text requests, sizes log-uniform 1 KiB-64 MiB (mean {mean / 1e6:.2f} MB), "
+                       f"70% compress / 30% decompress, 64 GB budget, {seconds:g} s per rate",
+           "saturation_GBps": round(thr, 2), "lambda_sat_per_s": round(lam_sat, 1), "rates": []}
+    for f in rates:
+        lam = f * lam_sat
+        count = max(20, int(lam * seconds))
+        reqs, arr, idx = make(count, lam)
+        sample = set(rng.choice(len(reqs), size=min(100, len(reqs)), replace=False).tolist())
+        res, lat, thr, good = run(reqs, arr, keep=sample)
+        ok = check_and_release(reqs, idx, res, sample)
+        out["rates"].append({"load": f, "lambda_per_s": round(lam, 1), "requests": count,
+                             "throughput_GBps": round(thr, 2), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
+                             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "all_ok": bool(good and ok)})
+    st = srv.stats()
+    out["batches"] = st["batches"]
+    for r in base:
+        srv.release(r["handle"])
+    srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +232,11 @@ def main():
     ap.add_argument("--cpu-passes", type=int, default=4)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true", help="also run the plain copy kernel (counter calibration)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the many-file batch leg")
+    ap.add_argument("--batch-files", type=int, default=4096)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--serve-seconds", type=float, default=2.0)
+    ap.add_argument("--serve-pool", type=int, default=384)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -197,6 +352,10 @@ def main():
                                 "sample": f"the whole {n}-byte workload, histogram+codebook+encode+decode, "
                                           f"{passes} passes averaged (plain serial C, one thread)"}
         line["bitexact_vs_oracle"] = bitexact
+    if not args.no_batch:
+        line["batch"] = batch_leg(P, codec, args.batch_files, 10)
+    if not args.no_serve:
+        line["serving"] = serve_leg(P, args.serve_seconds, args.serve_pool, (0.25, 0.5, 0.9, 1.2))
     print(json.dumps(line), flush=True)
 
 

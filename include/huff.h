@@ -83,7 +83,9 @@ typedef struct huff_codebook {
 /*
  * Device-resident codebook: everything the encoder and the decoder read.
  * Built on the device by huff_build_codebook_device() or from host lengths by
- * huff_codebook_upload(); fixed size, 256-byte aligned by the caller.
+ * huff_codebook_upload(); fixed size.  Its address must be a multiple of 16
+ * (the encoder copies its tables with 16-byte transfers); calls given a
+ * misaligned d_cb return HUFF_E_INVAL.
  */
 typedef struct huff_dcb {
     uint32_t nsym;                /* K */
@@ -202,8 +204,141 @@ huff_status huff_decode(huff_ctx* ctx, const uint32_t* d_words, uint64_t nwords,
  */
 huff_status huff_copy(huff_ctx* ctx, const void* d_src, void* d_dst, uint64_t bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Batches: many independent files, each with its own histogram, codebook and
+ * stream (Method 1 applied per file, as Method 2 applies it per segment).
+ * A batch plan is built once on the host; its calls then launch a fixed
+ * sequence of persistent kernels over all files at once (no per-file
+ * launches, no host synchronisation, no allocation), which is what makes
+ * them capturable in a HIP graph (huff_batch_run with use_graph).
+ * ------------------------------------------------------------------------ */
+typedef struct huff_file {
+    const uint8_t* in;   /* device: the file's bytes (compress / encode input) */
+    uint64_t n;          /* file length in bytes (< 2^38) */
+    huff_dcb* cb;        /* device: its codebook (compress writes it; encode and decode read it); 16-byte aligned */
+    uint32_t* words;     /* device: its encoded words (16-byte aligned); compress / encode write, decode reads */
+    uint64_t cap_words;  /* capacity of words (encode) / words valid (decode) */
+    uint64_t* chunk_off; /* device: nchunks + 1 segment offsets */
+    uint32_t* sub_lo;    /* device: nsub + 1 decode-index entries, or NULL when the batch has no sub index */
+    uint8_t* out;        /* device: decode output (n bytes), or NULL if the batch is never decoded */
+    uint64_t* hist;      /* device: 256-entry histogram written by compress, or NULL */
+    int32_t* status;     /* device: the file's status word, or NULL for the context's */
+} huff_file;
+
+typedef struct huff_batch huff_batch;
+
+enum { HUFF_OP_COMPRESS = 0, HUFF_OP_ENCODE = 1, HUFF_OP_DECODE = 2 };
+
+/*
+ * Plan a batch of nfiles files (host array, copied) with one chunk_size and
+ * sub_size for all.  Allocates the plan's device tables (tile -> file map,
+ * per-tile histograms and offsets), sized for these files.  The plan belongs
+ * to ctx's device and is freed by huff_batch_destroy.  Returns HUFF_E_INVAL
+ * for a bad file (null pointer with n > 0, misaligned cb or words, n too
+ * large) and HUFF_E_NOMEM if the tables do not fit.
+ */
+huff_status huff_batch_create(huff_ctx* ctx, const huff_file* files, uint32_t nfiles, uint32_t chunk_size,
+                              uint32_t sub_size, huff_batch** out);
+void huff_batch_destroy(huff_batch* batch);
+
+/*
+ * Runs one operation over every file of the batch on `stream`:
+ *   HUFF_OP_COMPRESS: per-file histogram and codebook (into files[i].cb),
+ *                     then encode;
+ *   HUFF_OP_ENCODE:   encode with the codebooks already in files[i].cb;
+ *   HUFF_OP_DECODE:   decode every file into files[i].out.
+ * Results are bit-identical to the single-file calls on each file.  With
+ * use_graph != 0 the launch sequence of this operation is captured into a
+ * HIP graph on first use and replayed afterwards (the files' buffers must
+ * then stay the same).  Errors found on the device go to files[i].status.
+ */
+huff_status huff_batch_run(huff_batch* batch, int op, int use_graph, void* stream);
+
+/* The three operations by name (no graph). */
+huff_status huff_compress_batch(huff_batch* batch, void* stream);
+huff_status huff_encode_batch(huff_batch* batch, void* stream);
+huff_status huff_decode_batch(huff_batch* batch, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Request server: a request loop that admits compress and decompress
+ * requests of mixed sizes against a device-memory budget, keeps compressed
+ * streams (codebook, words, indexes) resident on the device, and batches the
+ * requests that are waiting whenever a launch slot is free (continuous
+ * batching: requests arriving while others are on the GPU join the next
+ * batch, which runs concurrently on another stream).  Each request's result
+ * is bit-identical to the single-stream calls on the same data.
+ * A server thread owns the scheduling; the calls below are thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct huff_server huff_server;
+
+typedef struct huff_server_cfg {
+    uint64_t mem_budget_bytes; /* device memory for resident streams, outputs and batch tables (0: 1 GiB) */
+    uint32_t nslots;           /* batches in flight at once, one stream each (0: 2) */
+    uint32_t max_batch;        /* requests per batch (0: 512) */
+    uint32_t chunk_size;       /* segment size of compressed streams (0: 256 KiB) */
+    uint32_t sub_size;         /* decode index granularity, 0 for none (default 0) */
+} huff_server_cfg;
+
+enum { HUFF_REQ_DISCARD = 1 }; /* request flag: free the result's device memory as soon as it is done */
+
+typedef struct huff_request {
+    int32_t op;             /* HUFF_OP_COMPRESS or HUFF_OP_DECODE */
+    uint32_t flags;         /* HUFF_REQ_* */
+    const uint8_t* d_in;    /* compress: device input of n bytes, caller-owned until the request is done */
+    uint64_t n;             /* compress: input length */
+    uint64_t stream_handle; /* decode: a resident stream (result of a finished compress) */
+} huff_request;
+
+typedef struct huff_result {
+    int32_t status;         /* HUFF_OK or the request's error */
+    uint64_t handle;        /* compress: the resident stream; decode: the output buffer (release both);
+                               0 with HUFF_REQ_DISCARD */
+    uint64_t in_bytes;      /* bytes the request consumed (compress: n; decode: encoded bytes) */
+    uint64_t out_bytes;     /* compress: encoded bytes (ceil(T/8)); decode: n */
+    double t_submit, t_start, t_done; /* seconds on a steady clock: submitted, launched, seen complete */
+} huff_result;
+
+typedef struct huff_stream_info {
+    uint64_t n;             /* original length */
+    uint64_t total_bits;    /* T (compress results) */
+    const huff_dcb* cb;     /* device pointers valid until the handle is released */
+    const uint32_t* words;
+    const uint64_t* chunk_off;
+    const uint32_t* sub_lo; /* NULL without a sub index */
+    const uint8_t* out;     /* decode results: the decoded bytes */
+} huff_stream_info;
+
+/* Creates a server on ctx's device (it takes over ctx: use another context
+   for other calls).  Reserves the memory budget up front. */
+huff_status huff_server_create(huff_ctx* ctx, const huff_server_cfg* cfg, huff_server** out);
+/* Queues a request; never blocks on the GPU.  HUFF_E_NOMEM if it can never
+   fit the budget, HUFF_E_NOTFOUND for an unknown stream handle. */
+huff_status huff_server_submit(huff_server* s, const huff_request* req, uint64_t* ticket);
+/* HUFF_E_AGAIN while pending; HUFF_OK once done (result filled, ticket
+   retired); HUFF_E_NOTFOUND for an unknown ticket. */
+huff_status huff_server_poll(huff_server* s, uint64_t ticket, huff_result* out);
+/* Blocks until the request is done, then as huff_server_poll. */
+huff_status huff_server_wait(huff_server* s, uint64_t ticket, huff_result* out);
+/* Device pointers of a resident stream or decode output. */
+huff_status huff_server_stream(huff_server* s, uint64_t handle, huff_stream_info* out);
+/* Frees a resident stream or decode output (deferred while a queued decode
+   still reads it). */
+huff_status huff_server_release(huff_server* s, uint64_t handle);
+/* Open-loop load generator: submits reqs[i] at arrival_s[i] seconds after
+   the call (spinning between arrivals), waits for all, fills results[i].
+   results[i].t_submit is the scheduled arrival time, so latency includes
+   any delay in submitting. */
+huff_status huff_server_replay(huff_server* s, const huff_request* reqs, const double* arrival_s, uint32_t count,
+                               huff_result* results);
+/* Counters: [0] batches launched, [1] requests done, [2] bytes in use of the
+   budget, [3] peak bytes in use, [4] requests waiting, [5] batches in flight. */
+huff_status huff_server_stats(huff_server* s, uint64_t out[6]);
+/* Drains the requests in flight, then frees everything. */
+void huff_server_destroy(huff_server* s);
+
 /* sizeof of the ABI structs, for bindings: 0 huff_dcb, 1 huff_codebook,
-   2 huff_params; 0 for any other value. */
+   2 huff_params, 3 huff_file, 4 huff_server_cfg, 5 huff_request,
+   6 huff_result, 7 huff_stream_info; 0 for any other value. */
 uint64_t huff_abi_sizeof(int which);
 
 #ifdef __cplusplus

@@ -13,9 +13,11 @@ import os
 
 import numpy as np
 
-from ._abi import (HuffCodebook, HuffDcb, HuffParams, ERRORS, HuffError, lib, load)
+from ._abi import (HuffCodebook, HuffDcb, HuffFile, HuffParams, HuffRequest, HuffResult, HuffServerCfg,
+                   HuffStreamInfo, ERRORS, HuffError, lib, load, HUFF_OP_COMPRESS, HUFF_OP_ENCODE, HUFF_OP_DECODE,
+                   HUFF_E_AGAIN)
 
-__all__ = ["Codec", "HuffError", "build_codebook", "encoded_bits", "dcb_to_host", "load", "DCB_BYTES"]
+__all__ = ["Codec", "Batch", "Server", "batch_buffers", "HuffError", "build_codebook", "encoded_bits", "dcb_to_host", "load", "DCB_BYTES"]
 
 DCB_BYTES = ctypes.sizeof(HuffDcb)
 
@@ -201,3 +203,171 @@ class Codec:
     def decompress(self, c: dict, out=None, status=None, stream=None):
         return self.decode(c["words"], c["words"].numel(), c["chunk_off"], c["n"], c["chunk_size"], c["dcb"],
                            c.get("sub_lo"), c.get("sub_size", 0), out=out, status=status, stream=stream)
+
+
+class Batch:
+    """A batch plan (``huff_batch``): many files, each with its own codebook,
+    handled by one fixed sequence of launches per operation.
+
+    ``files`` is a list of dicts of device tensors: ``in`` (uint8, n bytes),
+    ``cb`` (DCB_BYTES), ``words`` (int32 view of u32), ``chunk_off`` (int64),
+    optionally ``sub_lo`` (int32), ``out`` (uint8), ``hist`` (int64, 256),
+    ``status`` (int32, 1).  Tensors are referenced, not copied: keep them
+    alive and in place while the batch is used (a captured graph replays the
+    same addresses).
+    """
+
+    def __init__(self, codec: "Codec", files: list, chunk_size: int, sub_size: int = 0):
+        self.codec = codec
+        self.files = files
+        self.chunk_size, self.sub_size = chunk_size, sub_size
+        arr = (HuffFile * max(1, len(files)))()
+        for i, f in enumerate(files):
+            x = f.get("in")
+            n = int(f["n"]) if "n" in f else int(x.numel())
+            arr[i] = HuffFile(_ptr(x), n, _ptr(f["cb"]), _ptr(f.get("words")),
+                              0 if f.get("words") is None else f["words"].numel(), _ptr(f["chunk_off"]),
+                              _ptr(f.get("sub_lo")), _ptr(f.get("out")), _ptr(f.get("hist")), _ptr(f.get("status")))
+        h = ctypes.c_void_p()
+        _check(lib().huff_batch_create(codec._ctx, arr, len(files), chunk_size, sub_size, ctypes.byref(h)),
+               "huff_batch_create")
+        self._h = h
+
+    def run(self, op: int, graph: bool = False, stream=None):
+        _check(lib().huff_batch_run(self._h, op, int(graph), self.codec._stream(stream)), "huff_batch_run")
+
+    def compress(self, graph: bool = False, stream=None):
+        self.run(HUFF_OP_COMPRESS, graph, stream)
+
+    def encode(self, graph: bool = False, stream=None):
+        self.run(HUFF_OP_ENCODE, graph, stream)
+
+    def decode(self, graph: bool = False, stream=None):
+        self.run(HUFF_OP_DECODE, graph, stream)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().huff_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_buffers(codec: "Codec", inputs: list, chunk_size: int, sub_size: int = 0, decode: bool = True,
+                  bits_per_byte: int = 16) -> list:
+    """Allocates per-file output tensors for a batch over the device uint8
+    tensors `inputs`.  The word capacity holds `bits_per_byte` bits per input
+    byte (16 covers every codebook whose longest code has at most 16 bits; a
+    file that needs more reports HUFF_E_CAPACITY in its status word)."""
+    torch = _torch()
+    dev = codec.device
+    files = []
+    for x in inputs:
+        n = x.numel()
+        nch = (n + chunk_size - 1) // chunk_size
+        f = {"in": x, "n": n,
+             "cb": torch.empty(DCB_BYTES, dtype=torch.uint8, device=dev),
+             "words": torch.empty((n * bits_per_byte + 31) // 32 + 8, dtype=torch.int32, device=dev),
+             "chunk_off": torch.empty(nch + 1, dtype=torch.int64, device=dev),
+             "hist": torch.empty(256, dtype=torch.int64, device=dev),
+             "status": torch.zeros(1, dtype=torch.int32, device=dev)}
+        if sub_size:
+            f["sub_lo"] = torch.empty((n + sub_size - 1) // sub_size + 1, dtype=torch.int32, device=dev)
+        if decode:
+            f["out"] = torch.empty(n, dtype=torch.uint8, device=dev)
+        files.append(f)
+    return files
+
+
+class Server:
+    """The request server (``huff_server``) on a context of its own.
+
+    ``submit_compress(x)`` / ``submit_decode(handle)`` queue requests and
+    return tickets; ``wait(ticket)`` / ``poll(ticket)`` give result dicts;
+    ``stream(handle)`` gives device pointers of a resident stream or decode
+    output; ``release(handle)`` frees it; ``replay(...)`` drives an open-loop
+    arrival schedule natively."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 1 << 30, nslots: int = 2, max_batch: int = 512,
+                 chunk_size: int = 256 << 10, sub_size: int = 0, params: dict | None = None):
+        self.codec = Codec(device, params)  # the server takes this context over
+        cfg = HuffServerCfg(mem_budget, nslots, max_batch, chunk_size, sub_size)
+        h = ctypes.c_void_p()
+        _check(lib().huff_server_create(self.codec._ctx, ctypes.byref(cfg), ctypes.byref(h)), "huff_server_create")
+        self._h = h
+        self.chunk_size, self.sub_size = chunk_size, sub_size
+        self._keep = {}  # ticket -> input tensor, alive until the request is done
+
+    @staticmethod
+    def _res(r: HuffResult) -> dict:
+        return {k: getattr(r, k) for k, _ in HuffResult._fields_}
+
+    def submit_compress(self, x) -> int:
+        t = ctypes.c_uint64()
+        req = HuffRequest(HUFF_OP_COMPRESS, 0, _ptr(x), x.numel(), 0)
+        _check(lib().huff_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "huff_server_submit")
+        self._keep[t.value] = x
+        return t.value
+
+    def submit_decode(self, handle: int) -> int:
+        t = ctypes.c_uint64()
+        req = HuffRequest(HUFF_OP_DECODE, 0, None, 0, handle)
+        _check(lib().huff_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "huff_server_submit")
+        return t.value
+
+    def wait(self, ticket: int) -> dict:
+        r = HuffResult()
+        _check(lib().huff_server_wait(self._h, ticket, ctypes.byref(r)), "huff_server_wait")
+        self._keep.pop(ticket, None)
+        return self._res(r)
+
+    def poll(self, ticket: int):
+        r = HuffResult()
+        rc = lib().huff_server_poll(self._h, ticket, ctypes.byref(r))
+        if rc == HUFF_E_AGAIN:
+            return None
+        _check(rc, "huff_server_poll")
+        self._keep.pop(ticket, None)
+        return self._res(r)
+
+    def stream(self, handle: int) -> dict:
+        i = HuffStreamInfo()
+        _check(lib().huff_server_stream(self._h, handle, ctypes.byref(i)), "huff_server_stream")
+        return {k: getattr(i, k) for k, _ in HuffStreamInfo._fields_}
+
+    def release(self, handle: int):
+        _check(lib().huff_server_release(self._h, handle), "huff_server_release")
+
+    def replay(self, requests: list, arrivals, discard=None) -> list:
+        """requests: list of (op, tensor_or_None, handle); arrivals: seconds;
+        discard: indexes whose results are freed as soon as they are done."""
+        n = len(requests)
+        reqs = (HuffRequest * max(1, n))()
+        drop = set(discard or ())
+        for i, (op, x, h) in enumerate(requests):
+            reqs[i] = HuffRequest(op, 1 if i in drop else 0, _ptr(x), 0 if x is None else x.numel(), h or 0)
+        arr = np.ascontiguousarray(arrivals, dtype=np.float64)
+        res = (HuffResult * max(1, n))()
+        _check(lib().huff_server_replay(self._h, reqs, arr.ctypes.data, n, res), "huff_server_replay")
+        return [self._res(res[i]) for i in range(n)]
+
+    def stats(self) -> dict:
+        a = (ctypes.c_uint64 * 6)()
+        _check(lib().huff_server_stats(self._h, a), "huff_server_stats")
+        return dict(zip(("batches", "done", "mem_used", "mem_peak", "waiting", "inflight"), list(a)))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().huff_server_destroy(self._h)
+            self._h = None
+            self.codec.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

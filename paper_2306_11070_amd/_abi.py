@@ -37,6 +37,39 @@ class HuffParams(ctypes.Structure):
                 ("enc_blocks_per_cu", ctypes.c_uint32)]
 
 
+class HuffFile(ctypes.Structure):
+    _fields_ = [("in_", ctypes.c_void_p), ("n", ctypes.c_uint64), ("cb", ctypes.c_void_p), ("words", ctypes.c_void_p),
+                ("cap_words", ctypes.c_uint64), ("chunk_off", ctypes.c_void_p), ("sub_lo", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("hist", ctypes.c_void_p), ("status", ctypes.c_void_p)]
+
+
+HUFF_OP_COMPRESS, HUFF_OP_ENCODE, HUFF_OP_DECODE = 0, 1, 2
+
+
+class HuffServerCfg(ctypes.Structure):
+    _fields_ = [("mem_budget_bytes", ctypes.c_uint64), ("nslots", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("chunk_size", ctypes.c_uint32), ("sub_size", ctypes.c_uint32)]
+
+
+class HuffRequest(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_int32), ("flags", ctypes.c_uint32), ("d_in", ctypes.c_void_p), ("n", ctypes.c_uint64),
+                ("stream_handle", ctypes.c_uint64)]
+
+
+HUFF_REQ_DISCARD = 1
+
+
+class HuffResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("handle", ctypes.c_uint64), ("in_bytes", ctypes.c_uint64),
+                ("out_bytes", ctypes.c_uint64), ("t_submit", ctypes.c_double), ("t_start", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
+
+
+class HuffStreamInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint64), ("total_bits", ctypes.c_uint64), ("cb", ctypes.c_void_p),
+                ("words", ctypes.c_void_p), ("chunk_off", ctypes.c_void_p), ("sub_lo", ctypes.c_void_p),
+                ("out", ctypes.c_void_p)]
+
 #: every symbol include/huff.h declares, with (restype, argtypes)
 _vp, _u64, _u32, _i32, _int = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_int
 PROTOTYPES = {
@@ -56,6 +89,21 @@ PROTOTYPES = {
     "huff_decode": (_i32, [_vp, _vp, _u64, _vp, _u64, _u32, _vp, _u32, _vp, _vp, _vp, _vp]),
     "huff_copy": (_i32, [_vp, _vp, _vp, _u64, _vp]),
     "huff_abi_sizeof": (_u64, [_int]),
+    "huff_batch_create": (_i32, [_vp, _vp, _u32, _u32, _u32, _vp]),
+    "huff_batch_destroy": (None, [_vp]),
+    "huff_batch_run": (_i32, [_vp, _int, _int, _vp]),
+    "huff_compress_batch": (_i32, [_vp, _vp]),
+    "huff_encode_batch": (_i32, [_vp, _vp]),
+    "huff_decode_batch": (_i32, [_vp, _vp]),
+    "huff_server_create": (_i32, [_vp, _vp, _vp]),
+    "huff_server_submit": (_i32, [_vp, _vp, _vp]),
+    "huff_server_poll": (_i32, [_vp, _u64, _vp]),
+    "huff_server_wait": (_i32, [_vp, _u64, _vp]),
+    "huff_server_stream": (_i32, [_vp, _u64, _vp]),
+    "huff_server_release": (_i32, [_vp, _u64]),
+    "huff_server_replay": (_i32, [_vp, _vp, _vp, _u32, _vp]),
+    "huff_server_stats": (_i32, [_vp, _vp]),
+    "huff_server_destroy": (None, [_vp]),
 }
 
 _lib = None
@@ -74,7 +122,8 @@ def load(path: str = LIB_PATH):
         fn = getattr(l, name)
         fn.restype = res
         fn.argtypes = args
-    for i, cls in enumerate((HuffDcb, HuffCodebook, HuffParams)):
+    for i, cls in enumerate((HuffDcb, HuffCodebook, HuffParams, HuffFile, HuffServerCfg, HuffRequest, HuffResult,
+                             HuffStreamInfo)):
         if l.huff_abi_sizeof(i) != ctypes.sizeof(cls):
             raise ImportError(f"ABI mismatch for {cls.__name__}: C {l.huff_abi_sizeof(i)} vs ctypes {ctypes.sizeof(cls)}")
     _lib = l

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhuff.so")
-SOURCES = ["kernels.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "api.cpp", "server.cpp"]
 ARCH = "gfx950"
 
 
@@ -26,7 +26,7 @@ def build(verbose: bool = False) -> str:
     """Compiles every source (always) and links libhuff.so."""
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
-           # packed fp32 ops stay off (see DESIGN.md); the host pass ignores the flag
+           # packed fp32 instructions stay off in device code; the host pass ignores the flag
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",
            "-I", INCLUDE, "-I", CSRC]

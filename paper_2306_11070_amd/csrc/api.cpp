@@ -5,48 +5,19 @@
 
 #include <algorithm>
 #include <mutex>
+#include <new>
+#include <vector>
 
-#include "common.h"
+#include "runtime.h"
 
 using namespace huff;
 
-struct huff_ctx {
-    int device = 0;
-    int num_cus = 256;
-    huff_params params{};
-    HistState* hist_st = nullptr;
-    // encode tile workspaces, sized for tile_cap tiles
-    uint16_t* tile_hist = nullptr;        // [tile_cap][256]
-    uint32_t* tile_bits = nullptr;        // [tile_cap]
-    uint32_t* tile_local = nullptr;       // [tile_cap]
-    unsigned long long* blk_total = nullptr;  // [tile_cap / 1024 + 1]
-    uint64_t tile_cap = 0;
-    int32_t* status = nullptr;
-};
-
 namespace {
 
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-    }
-};
-
-inline bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
-inline uint32_t log2u(uint64_t x) { return 63 - __builtin_clzll(x); }
-inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
-
-huff_status hip_status(hipError_t e) { return e == hipSuccess ? HUFF_OK : HUFF_E_HIP; }
 
 huff_params defaults(int num_cus) {
     huff_params p;
-    p.enc_blocks_per_cu = 4;
+    p.enc_blocks_per_cu = 3;  // LDS allows three encode workgroups per CU
     p.hist_blocks = (uint32_t)num_cus * 2;
     p.hist_depth = 16;
     p.dec_block = 256;
@@ -77,16 +48,18 @@ huff_status ensure_tiles(huff_ctx* ctx, uint64_t tiles) {
     (void)hipFree(ctx->tile_hist);
     (void)hipFree(ctx->tile_bits);
     (void)hipFree(ctx->tile_local);
-    (void)hipFree(ctx->blk_total);
+    (void)hipFree(ctx->blk_tail);
+    (void)hipFree(ctx->blk_carry);
     ctx->tile_hist = nullptr;
     ctx->tile_bits = ctx->tile_local = nullptr;
-    ctx->blk_total = nullptr;
+    ctx->blk_tail = ctx->blk_carry = nullptr;
     ctx->tile_cap = 0;
     const uint64_t blocks = cap / kScanTilesPerBlock + 1;
     if (hipMalloc(&ctx->tile_hist, cap * 256 * sizeof(uint16_t)) != hipSuccess ||
         hipMalloc(&ctx->tile_bits, cap * sizeof(uint32_t)) != hipSuccess ||
         hipMalloc(&ctx->tile_local, cap * sizeof(uint32_t)) != hipSuccess ||
-        hipMalloc(&ctx->blk_total, blocks * sizeof(unsigned long long)) != hipSuccess)
+        hipMalloc(&ctx->blk_tail, blocks * sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc(&ctx->blk_carry, blocks * sizeof(unsigned long long)) != hipSuccess)
         return HUFF_E_NOMEM;
     ctx->tile_cap = cap;
     return HUFF_OK;
@@ -146,7 +119,8 @@ void huff_ctx_destroy(huff_ctx* c) {
     (void)hipFree(c->tile_hist);
     (void)hipFree(c->tile_bits);
     (void)hipFree(c->tile_local);
-    (void)hipFree(c->blk_total);
+    (void)hipFree(c->blk_tail);
+    (void)hipFree(c->blk_carry);
     if (c->status) (void)hipFree(c->status);
     delete c;
 }
@@ -181,6 +155,7 @@ huff_status launch_hist_only(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint1
     const uint64_t tpb = (ntiles + blocks - 1) / blocks;
     blocks = (ntiles + tpb - 1) / tpb;
     HistArgs a;
+    memset(&a, 0, sizeof(a));
     a.in = d_in;
     a.n = n;
     a.st = c->hist_st;
@@ -217,10 +192,14 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
     sa.tile_hist = from_hist ? c->tile_hist : nullptr;
     sa.tile_bits = from_hist ? nullptr : c->tile_bits;
     sa.cb = d_cb;
+    sa.files = nullptr;
+    sa.tile_file = nullptr;
     sa.ntiles = ntiles;
     sa.tile_local = c->tile_local;
-    sa.blk_total = c->blk_total;
+    sa.blk_tail = c->blk_tail;
     st = hip_status(launch_tile_scan(sa, s));
+    if (st != HUFF_OK) return st;
+    st = hip_status(launch_blk_scan(c->blk_tail, c->blk_carry, (ntiles + kScanTilesPerBlock - 1) / kScanTilesPerBlock, s));
     if (st != HUFF_OK) return st;
     EncArgs a;
     memset(&a, 0, sizeof(a));
@@ -237,9 +216,11 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
     a.nfiles = 1;
     a.chunk_log2 = log2u(chunk_size);
     a.sub_log2 = sub_size ? log2u(sub_size) : kNoSub;
+    a.aligned = ((uintptr_t)d_in & 15u) == 0;
     a.ntiles = ntiles;
+    a.tile_file = nullptr;
     a.tile_local = c->tile_local;
-    a.blk_total = c->blk_total;
+    a.blk_carry = c->blk_carry;
     a.err = c->status;
     const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)c->num_cus * c->params.enc_blocks_per_cu);
     return hip_status(launch_encode(a, (uint32_t)grid, s));
@@ -323,7 +304,7 @@ uint64_t huff_encoded_bits(const uint64_t hist[256], const huff_codebook* cb) {
 
 huff_status huff_build_codebook_device(huff_ctx* c, const uint64_t* d_hist, huff_dcb* d_cb, int32_t* d_status,
                                        void* stream) {
-    if (!c || !d_hist || !d_cb) return HUFF_E_INVAL;
+    if (!c || !d_hist || !dcb_ok(d_cb)) return HUFF_E_INVAL;
     DeviceGuard g(c->device);
     CbArgs a;
     memset(&a, 0, sizeof(a));
@@ -331,11 +312,11 @@ huff_status huff_build_codebook_device(huff_ctx* c, const uint64_t* d_hist, huff
     a.out = d_cb;
     a.err = d_status ? d_status : c->status;
     a.from_lengths = 0;
-    return hip_status(launch_codebook(a, as_stream(stream)));
+    return hip_status(launch_codebook(a, 1, as_stream(stream)));
 }
 
 huff_status huff_codebook_upload(huff_ctx* c, const huff_codebook* cb, huff_dcb* d_cb, void* stream) {
-    if (!c || !cb || !d_cb) return HUFF_E_INVAL;
+    if (!c || !cb || !dcb_ok(d_cb)) return HUFF_E_INVAL;
     // lengths must describe a prefix code: Kraft sum <= 1, exactly
     unsigned __int128 kraft = 0;
     const unsigned __int128 one = (unsigned __int128)1 << HUFF_MAX_CODE_LEN;
@@ -351,13 +332,13 @@ huff_status huff_codebook_upload(huff_ctx* c, const huff_codebook* cb, huff_dcb*
     a.err = c->status;
     a.from_lengths = 1;
     memcpy(a.len, cb->len, 256);
-    return hip_status(launch_codebook(a, as_stream(stream)));
+    return hip_status(launch_codebook(a, 1, as_stream(stream)));
 }
 
 huff_status huff_encode(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff_dcb* d_cb, uint32_t chunk_size,
                         uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off, uint32_t sub_size,
                         uint32_t* d_sub_lo, int32_t* d_status, void* stream) {
-    if (!c || !d_cb) return HUFF_E_INVAL;
+    if (!c || !dcb_ok(d_cb)) return HUFF_E_INVAL;
     huff_status st = check_encode_args(n, d_in, d_words, d_chunk_off, chunk_size, sub_size, d_sub_lo);
     if (st != HUFF_OK) return st;
     DeviceGuard g(c->device);
@@ -368,7 +349,7 @@ huff_status huff_encode(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff
 huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t chunk_size, huff_dcb* d_cb,
                           uint64_t* d_hist, uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off,
                           uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, void* stream) {
-    if (!c || !d_cb) return HUFF_E_INVAL;
+    if (!c || !dcb_ok(d_cb)) return HUFF_E_INVAL;
     huff_status st = check_encode_args(n, d_in, d_words, d_chunk_off, chunk_size, sub_size, d_sub_lo);
     if (st != HUFF_OK) return st;
     DeviceGuard g(c->device);
@@ -385,7 +366,7 @@ huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t
     a.hist_out = d_hist;
     a.out = d_cb;
     a.err = d_status ? d_status : c->status;
-    st = hip_status(launch_codebook(a, s));
+    st = hip_status(launch_codebook(a, 1, s));
     if (st != HUFF_OK) return st;
     return launch_encode_one(c, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
                              d_status, true, s);
@@ -394,7 +375,7 @@ huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t
 huff_status huff_decode(huff_ctx* c, const uint32_t* d_words, uint64_t nwords, const uint64_t* d_chunk_off,
                         uint64_t n, uint32_t chunk_size, const uint32_t* d_sub_lo, uint32_t sub_size,
                         const huff_dcb* d_cb, uint8_t* d_out, int32_t* d_status, void* stream) {
-    if (!c || !d_cb || !d_chunk_off || n >= kMaxN) return HUFF_E_INVAL;
+    if (!c || !dcb_ok(d_cb) || !d_chunk_off || n >= kMaxN) return HUFF_E_INVAL;
     if (!is_pow2(chunk_size) || chunk_size < 1024 || chunk_size > (64u << 20)) return HUFF_E_INVAL;
     if (sub_size && (!is_pow2(sub_size) || sub_size < 16 || sub_size > chunk_size || !d_sub_lo)) return HUFF_E_INVAL;
     if (n == 0) return HUFF_OK;
@@ -437,6 +418,234 @@ extern "C" uint64_t huff_abi_sizeof(int which) {
         case 0: return sizeof(huff_dcb);
         case 1: return sizeof(huff_codebook);
         case 2: return sizeof(huff_params);
+        case 3: return sizeof(huff_file);
+        case 4: return sizeof(huff_server_cfg);
+        case 5: return sizeof(huff_request);
+        case 6: return sizeof(huff_result);
+        case 7: return sizeof(huff_stream_info);
         default: return 0;
     }
 }
+
+// =============================================================== batches
+namespace huff {
+
+huff_status batch_tables(const huff_file* files, uint32_t nfiles, uint32_t chunk_size, uint32_t sub_size,
+                         BatchTables& t, bool decode_only) {
+    if (nfiles && !files) return HUFF_E_INVAL;
+    if (!is_pow2(chunk_size) || chunk_size < 1024 || chunk_size > (64u << 20)) return HUFF_E_INVAL;
+    if (sub_size && (!is_pow2(sub_size) || sub_size < 16 || sub_size > chunk_size)) return HUFF_E_INVAL;
+    t.enc.assign(nfiles, FileDesc{});
+    t.dec.assign(nfiles, FileDesc{});
+    t.ntiles = t.nitems = 0;
+    t.aligned = true;
+    const uint32_t item = sub_size ? sub_size : chunk_size;
+    for (uint32_t i = 0; i < nfiles; ++i) {
+        const huff_file& f = files[i];
+        if (f.n >= kMaxN || !dcb_ok(f.cb) || !f.chunk_off || (sub_size && !f.sub_lo)) return HUFF_E_INVAL;
+        if (f.n && ((!decode_only && !f.in) || !f.words || ((uintptr_t)f.words & 15u))) return HUFF_E_INVAL;
+        if (f.n && decode_only && !f.out) return HUFF_E_INVAL;
+        FileDesc d;
+        memset(&d, 0, sizeof(d));
+        d.in = f.in;
+        d.n = f.n;
+        d.cb = f.cb;
+        d.words = f.words;
+        d.nwords = f.cap_words;
+        d.chunk_off = f.chunk_off;
+        d.sub_lo = sub_size ? f.sub_lo : nullptr;
+        d.out = f.out;
+        d.status = f.status;
+        d.hist = f.hist;
+        d.first = t.ntiles;
+        t.enc[i] = d;
+        d.first = t.nitems;
+        t.dec[i] = d;
+        t.ntiles += (f.n + kEncTile - 1) / kEncTile;
+        const uint64_t items = (f.n + item - 1) / item;
+        t.nitems += (items + kDecBatchBlock - 1) / kDecBatchBlock * kDecBatchBlock;
+        if (f.n && ((uintptr_t)f.in & 15u)) t.aligned = false;
+    }
+    if (t.ntiles >= (1ull << 32)) return HUFF_E_INVAL;
+    t.tile_file.resize(t.ntiles);
+    for (uint32_t i = 0; i < nfiles; ++i) {
+        const uint64_t t0 = t.enc[i].first, t1 = t0 + (files[i].n + kEncTile - 1) / kEncTile;
+        for (uint64_t k = t0; k < t1; ++k) t.tile_file[k] = i;
+    }
+    return HUFF_OK;
+}
+
+uint64_t batch_workspace_bytes(uint64_t ntiles) {
+    const uint64_t nblk = ntiles / kScanTilesPerBlock + 1;
+    return ntiles * (4 + 512 + 4) + nblk * 16;
+}
+
+huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
+    huff_ctx* c = b->ctx;
+    if (op == HUFF_OP_DECODE) {
+        if (b->nitems == 0) return HUFF_OK;
+        const uint32_t item = b->sub_size ? b->sub_size : b->chunk_size;
+        DecArgs a;
+        memset(&a, 0, sizeof(a));
+        a.files = b->d_dec;
+        a.nfiles = b->nfiles;
+        a.chunk_log2 = log2u(b->chunk_size);
+        a.item_log2 = log2u(item);
+        a.use_sub = b->sub_size ? 1 : 0;
+        a.nitems = b->nitems;
+        a.err = c->status;
+        return hip_status(launch_decode(a, kDecBatchBlock, s));
+    }
+    if (b->ntiles > 0) {
+        // per-tile histograms of every file
+        HistArgs h;
+        memset(&h, 0, sizeof(h));
+        h.files = b->d_enc;
+        h.tile_file = b->d_tile_file;
+        h.ntiles = b->ntiles;
+        h.tile_hist = b->d_tile_hist;
+        h.depth_log2 = log2u(c->params.hist_depth);
+        uint64_t blocks = std::min<uint64_t>(c->params.hist_blocks, b->ntiles);
+        const uint64_t tpb = (b->ntiles + blocks - 1) / blocks;
+        h.tiles_per_block = tpb;
+        blocks = (b->ntiles + tpb - 1) / tpb;
+        huff_status st = hip_status(launch_histogram(h, (uint32_t)blocks, s));
+        if (st != HUFF_OK) return st;
+    }
+    if (op == HUFF_OP_COMPRESS && b->nfiles) {
+        // one codebook per file from its tiles' histograms (empty files too)
+        CbArgs a;
+        memset(&a, 0, sizeof(a));
+        a.files = b->d_enc;
+        a.tile_hist = b->d_tile_hist;
+        a.err = c->status;
+        huff_status st = hip_status(launch_codebook(a, b->nfiles, s));
+        if (st != HUFF_OK) return st;
+    }
+    if (b->ntiles == 0) return HUFF_OK;
+    ScanArgs sa;
+    memset(&sa, 0, sizeof(sa));
+    sa.tile_hist = b->d_tile_hist;
+    sa.files = b->d_enc;
+    sa.tile_file = b->d_tile_file;
+    sa.ntiles = b->ntiles;
+    sa.tile_local = b->d_tile_local;
+    sa.blk_tail = b->d_blk_tail;
+    huff_status st = hip_status(launch_tile_scan(sa, s));
+    if (st != HUFF_OK) return st;
+    st = hip_status(launch_blk_scan(b->d_blk_tail, b->d_blk_carry, (b->ntiles + kScanTilesPerBlock - 1) / kScanTilesPerBlock, s));
+    if (st != HUFF_OK) return st;
+    EncArgs e;
+    memset(&e, 0, sizeof(e));
+    e.files = b->d_enc;
+    e.nfiles = b->nfiles;
+    e.chunk_log2 = log2u(b->chunk_size);
+    e.sub_log2 = b->sub_size ? log2u(b->sub_size) : kNoSub;
+    e.aligned = b->aligned ? 1u : 0u;
+    e.ntiles = b->ntiles;
+    e.tile_file = b->d_tile_file;
+    e.tile_local = b->d_tile_local;
+    e.blk_carry = b->d_blk_carry;
+    e.err = c->status;
+    const uint64_t grid = std::min<uint64_t>(b->ntiles, (uint64_t)c->num_cus * c->params.enc_blocks_per_cu);
+    return hip_status(launch_encode(e, (uint32_t)grid, s));
+}
+
+}  // namespace huff
+
+namespace {
+void batch_free(huff_batch* b) {
+    for (int i = 0; i < 3; ++i) {
+        if (b->exec[i]) (void)hipGraphExecDestroy(b->exec[i]);
+        if (b->graph[i]) (void)hipGraphDestroy(b->graph[i]);
+    }
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->owns) {
+        (void)hipFree(b->d_enc);
+        (void)hipFree(b->d_dec);
+        (void)hipFree(b->d_tile_file);
+        (void)hipFree(b->d_tile_hist);
+        (void)hipFree(b->d_tile_local);
+        (void)hipFree(b->d_blk_tail);
+        (void)hipFree(b->d_blk_carry);
+    }
+    delete b;
+}
+}  // namespace
+
+extern "C" {
+
+huff_status huff_batch_create(huff_ctx* c, const huff_file* files, uint32_t nfiles, uint32_t chunk_size,
+                              uint32_t sub_size, huff_batch** out) {
+    if (!out) return HUFF_E_INVAL;
+    *out = nullptr;
+    if (!c) return HUFF_E_INVAL;
+    BatchTables t;
+    const huff_status vst = batch_tables(files, nfiles, chunk_size, sub_size, t);
+    if (vst != HUFF_OK) return vst;
+    DeviceGuard g(c->device);
+    huff_batch* b = new (std::nothrow) huff_batch();
+    if (!b) return HUFF_E_NOMEM;
+    b->ctx = c;
+    b->nfiles = nfiles;
+    b->chunk_size = chunk_size;
+    b->sub_size = sub_size;
+    b->ntiles = t.ntiles;
+    b->nitems = t.nitems;
+    b->aligned = t.aligned;
+    const uint64_t ntiles = t.ntiles;
+    const uint64_t nblk = ntiles / kScanTilesPerBlock + 1;
+    const size_t fbytes = std::max<size_t>(1, nfiles) * sizeof(FileDesc);
+    bool ok = hipMalloc(&b->d_enc, fbytes) == hipSuccess && hipMalloc(&b->d_dec, fbytes) == hipSuccess &&
+              hipMalloc(&b->d_tile_file, std::max<uint64_t>(1, ntiles) * 4) == hipSuccess &&
+              hipMalloc(&b->d_tile_hist, std::max<uint64_t>(1, ntiles) * 512) == hipSuccess &&
+              hipMalloc(&b->d_tile_local, std::max<uint64_t>(1, ntiles) * 4) == hipSuccess &&
+              hipMalloc(&b->d_blk_tail, nblk * 8) == hipSuccess && hipMalloc(&b->d_blk_carry, nblk * 8) == hipSuccess;
+    if (!ok) { batch_free(b); return HUFF_E_NOMEM; }
+    if ((nfiles && (hipMemcpy(b->d_enc, t.enc.data(), nfiles * sizeof(FileDesc), hipMemcpyHostToDevice) != hipSuccess ||
+                    hipMemcpy(b->d_dec, t.dec.data(), nfiles * sizeof(FileDesc), hipMemcpyHostToDevice) != hipSuccess)) ||
+        (ntiles && hipMemcpy(b->d_tile_file, t.tile_file.data(), ntiles * 4, hipMemcpyHostToDevice) != hipSuccess)) {
+        batch_free(b);
+        return HUFF_E_HIP;
+    }
+    *out = b;
+    return HUFF_OK;
+}
+
+void huff_batch_destroy(huff_batch* b) {
+    if (!b) return;
+    DeviceGuard g(b->ctx->device);
+    (void)hipDeviceSynchronize();
+    batch_free(b);
+}
+
+huff_status huff_batch_run(huff_batch* b, int op, int use_graph, void* stream) {
+    if (!b || op < HUFF_OP_COMPRESS || op > HUFF_OP_DECODE) return HUFF_E_INVAL;
+    DeviceGuard g(b->ctx->device);
+    hipStream_t s = as_stream(stream);
+    if (!use_graph) return batch_launch(b, op, s);
+    if (!b->exec[op]) {
+        if (!b->cap && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) return HUFF_E_HIP;
+        if (hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess) return HUFF_E_HIP;
+        const huff_status st = batch_launch(b, op, b->cap);
+        hipGraph_t gr = nullptr;
+        const hipError_t e = hipStreamEndCapture(b->cap, &gr);
+        if (st != HUFF_OK || e != hipSuccess || !gr) {
+            if (gr) (void)hipGraphDestroy(gr);
+            return st != HUFF_OK ? st : HUFF_E_HIP;
+        }
+        if (hipGraphInstantiate(&b->exec[op], gr, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(gr);
+            b->exec[op] = nullptr;
+            return HUFF_E_HIP;
+        }
+        b->graph[op] = gr;
+    }
+    return hip_status(hipGraphLaunch(b->exec[op], s));
+}
+
+huff_status huff_compress_batch(huff_batch* b, void* stream) { return huff_batch_run(b, HUFF_OP_COMPRESS, 0, stream); }
+huff_status huff_encode_batch(huff_batch* b, void* stream) { return huff_batch_run(b, HUFF_OP_ENCODE, 0, stream); }
+huff_status huff_decode_batch(huff_batch* b, void* stream) { return huff_batch_run(b, HUFF_OP_DECODE, 0, stream); }
+
+}  // extern "C"

@@ -40,6 +40,7 @@ struct FileDesc {
     uint32_t* sub_lo;         // nsub + 1 or null
     uint8_t* out;             // decode output
     int32_t* status;          // per-file status word (may be null)
+    uint64_t* hist;           // batch codebook: optional histogram output
     uint64_t first;           // first global work item (tile / sub-block) of this file
 };
 
@@ -49,19 +50,31 @@ struct EncArgs {
     uint32_t nfiles;
     uint32_t chunk_log2;
     uint32_t sub_log2;      // kNoSub if no sub index
+    uint32_t aligned;       // every input is 16-byte aligned
     uint64_t ntiles;        // total over all files
-    const uint32_t* tile_local;            // first bit of each tile inside its scan block
-    const unsigned long long* blk_total;   // code bits of each scan block
+    const uint32_t* tile_file;             // batch: file index of every tile
+    const uint32_t* tile_local;            // tile's first bit inside (its scan block and its file)
+    const unsigned long long* blk_carry;   // bits of the file open at a scan block's start, before the block
     int32_t* err;           // fallback status word
 };
+
+// Tile offsets are a scan segmented by file, in two levels: k_tile_scan
+// scans the tiles of each 1024-tile block, k_blk_scan carries the open
+// file's running total from block to block.  blk_tail packs, per block, the
+// bits of its last segment (low 62 bits) with two flags.
+constexpr unsigned long long kTailStarts = 1ull << 63;  // the block's last segment starts inside the block
+constexpr unsigned long long kTailHead = 1ull << 62;    // a file starts at the block's first tile
+constexpr unsigned long long kTailBits = kTailHead - 1;
 
 struct ScanArgs {
     const uint16_t* tile_hist;  // per-tile histograms, or ...
     const uint32_t* tile_bits;  // ... per-tile bit counts
-    const huff_dcb* cb;
+    const huff_dcb* cb;         // single file: its codebook
+    const FileDesc* files;      // batch: file table (codebook per file) ...
+    const uint32_t* tile_file;  // ... and file index of every tile
     uint64_t ntiles;
     uint32_t* tile_local;
-    unsigned long long* blk_total;
+    unsigned long long* blk_tail;
 };
 
 struct DecArgs {
@@ -76,8 +89,11 @@ struct DecArgs {
 };
 
 struct HistArgs {
-    const uint8_t* in;
+    const uint8_t* in;          // single input ...
     uint64_t n;
+    const FileDesc* files;      // ... or a batch: file table, tile -> file map, tile count
+    const uint32_t* tile_file;
+    uint64_t ntiles;
     HistState* st;
     uint16_t* tile_hist;    // optional per-16 KiB-tile histograms, [ntiles][256]
     uint32_t depth_log2;
@@ -85,6 +101,8 @@ struct HistArgs {
 };
 
 struct CbArgs {
+    const FileDesc* files;      // batch: one workgroup per file, histogram summed from ...
+    const uint16_t* tile_hist;  // ... the per-tile histograms; output into files[i].cb
     const uint64_t* hist;   // histogram input (from-histogram mode) ...
     HistState* acc;         // ... or the histogram accumulator, summed and zeroed here
     uint64_t* hist_out;     // optional copy of the summed histogram (accumulator mode)
@@ -97,13 +115,16 @@ struct CbArgs {
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s);
-hipError_t launch_codebook(const CbArgs& a, hipStream_t s);
+hipError_t launch_codebook(const CbArgs& a, uint32_t nblocks, hipStream_t s);
 hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, uint32_t* tile_bits, hipStream_t s);
 hipError_t launch_tile_scan(const ScanArgs& a, hipStream_t s);
+hipError_t launch_blk_scan(const unsigned long long* blk_tail, unsigned long long* blk_carry, uint64_t nblk,
+                           hipStream_t s);
 hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo, hipStream_t s);
 hipError_t launch_decode(const DecArgs& a, uint32_t block, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
+hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
 
 }  // namespace huff

@@ -237,10 +237,13 @@ def test_launch_shapes_same_output(P, hist, dec_block, sub):
     c.close()
 
 
-def test_unaligned_input(codec):
-    _say("unaligned input")
-    a = _data("zipf96", 100_003)
-    x = dev(np.concatenate([np.zeros(5, np.uint8), a]))[5:]
+@pytest.mark.parametrize("off", [1, 4, 5, 12, 15])
+@pytest.mark.parametrize("kind", ["zipf96", "markov"])
+def test_unaligned_input(codec, off, kind):
+    """Inputs at every byte skew inside a 16-byte block, over several tiles."""
+    _say(f"unaligned input off={off} kind={kind}")
+    a = _data(kind, 100_003, seed=off)
+    x = dev(np.concatenate([np.zeros(off, np.uint8), a]))[off:]
     st = codec.new_status()
     c = codec.compress(x, 1024, 128, status=st)
     _check_status(st)
