@@ -189,17 +189,14 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
         if (st != HUFF_OK) return st;
     }
     ScanArgs sa;
+    memset(&sa, 0, sizeof(sa));
     sa.tile_hist = from_hist ? c->tile_hist : nullptr;
     sa.tile_bits = from_hist ? nullptr : c->tile_bits;
     sa.cb = d_cb;
-    sa.files = nullptr;
-    sa.tile_file = nullptr;
     sa.ntiles = ntiles;
     sa.tile_local = c->tile_local;
-    sa.blk_tail = c->blk_tail;
+    sa.blk_total = c->blk_tail;  // one stream: the block-tail buffer holds block totals
     st = hip_status(launch_tile_scan(sa, s));
-    if (st != HUFF_OK) return st;
-    st = hip_status(launch_blk_scan(c->blk_tail, c->blk_carry, (ntiles + kScanTilesPerBlock - 1) / kScanTilesPerBlock, s));
     if (st != HUFF_OK) return st;
     EncArgs a;
     memset(&a, 0, sizeof(a));
@@ -216,11 +213,9 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
     a.nfiles = 1;
     a.chunk_log2 = log2u(chunk_size);
     a.sub_log2 = sub_size ? log2u(sub_size) : kNoSub;
-    a.aligned = ((uintptr_t)d_in & 15u) == 0;
     a.ntiles = ntiles;
-    a.tile_file = nullptr;
     a.tile_local = c->tile_local;
-    a.blk_carry = c->blk_carry;
+    a.blk_total = c->blk_tail;
     a.err = c->status;
     const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)c->num_cus * c->params.enc_blocks_per_cu);
     return hip_status(launch_encode(a, (uint32_t)grid, s));
@@ -438,7 +433,6 @@ huff_status batch_tables(const huff_file* files, uint32_t nfiles, uint32_t chunk
     t.enc.assign(nfiles, FileDesc{});
     t.dec.assign(nfiles, FileDesc{});
     t.ntiles = t.nitems = 0;
-    t.aligned = true;
     const uint32_t item = sub_size ? sub_size : chunk_size;
     for (uint32_t i = 0; i < nfiles; ++i) {
         const huff_file& f = files[i];
@@ -464,7 +458,6 @@ huff_status batch_tables(const huff_file* files, uint32_t nfiles, uint32_t chunk
         t.ntiles += (f.n + kEncTile - 1) / kEncTile;
         const uint64_t items = (f.n + item - 1) / item;
         t.nitems += (items + kDecBatchBlock - 1) / kDecBatchBlock * kDecBatchBlock;
-        if (f.n && ((uintptr_t)f.in & 15u)) t.aligned = false;
     }
     if (t.ntiles >= (1ull << 32)) return HUFF_E_INVAL;
     t.tile_file.resize(t.ntiles);
@@ -541,7 +534,6 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
     e.nfiles = b->nfiles;
     e.chunk_log2 = log2u(b->chunk_size);
     e.sub_log2 = b->sub_size ? log2u(b->sub_size) : kNoSub;
-    e.aligned = b->aligned ? 1u : 0u;
     e.ntiles = b->ntiles;
     e.tile_file = b->d_tile_file;
     e.tile_local = b->d_tile_local;
@@ -587,12 +579,12 @@ huff_status huff_batch_create(huff_ctx* c, const huff_file* files, uint32_t nfil
     huff_batch* b = new (std::nothrow) huff_batch();
     if (!b) return HUFF_E_NOMEM;
     b->ctx = c;
+    b->device = c->device;
     b->nfiles = nfiles;
     b->chunk_size = chunk_size;
     b->sub_size = sub_size;
     b->ntiles = t.ntiles;
     b->nitems = t.nitems;
-    b->aligned = t.aligned;
     const uint64_t ntiles = t.ntiles;
     const uint64_t nblk = ntiles / kScanTilesPerBlock + 1;
     const size_t fbytes = std::max<size_t>(1, nfiles) * sizeof(FileDesc);
@@ -614,14 +606,14 @@ huff_status huff_batch_create(huff_ctx* c, const huff_file* files, uint32_t nfil
 
 void huff_batch_destroy(huff_batch* b) {
     if (!b) return;
-    DeviceGuard g(b->ctx->device);
+    DeviceGuard g(b->device);
     (void)hipDeviceSynchronize();
     batch_free(b);
 }
 
 huff_status huff_batch_run(huff_batch* b, int op, int use_graph, void* stream) {
     if (!b || op < HUFF_OP_COMPRESS || op > HUFF_OP_DECODE) return HUFF_E_INVAL;
-    DeviceGuard g(b->ctx->device);
+    DeviceGuard g(b->device);
     hipStream_t s = as_stream(stream);
     if (!use_graph) return batch_launch(b, op, s);
     if (!b->exec[op]) {

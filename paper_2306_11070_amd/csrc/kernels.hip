@@ -270,26 +270,26 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
     if (v < 64) s_cnt[v] = 0;
     huff_dcb* d = a.out;
     int32_t* err = a.err;
-    if (a.files) {
-        // one workgroup per file: its histogram is the sum of its tiles'
-        const FileDesc& f = a.files[blockIdx.x];
-        d = const_cast<huff_dcb*>(f.cb);  // the batch builds the codebooks it then reads
-        if (f.status) err = f.status;
-        const uint64_t t0 = f.first, t1 = f.first + (f.n + kEncTile - 1) / kEncTile;
-        uint64_t acc4[4] = {0, 0, 0, 0};
-        uint64_t t = t0;
-        for (; t + 4 <= t1; t += 4)
+    if (!a.from_lengths) {
+        if (a.files) {
+            // one workgroup per file: its histogram is the sum of its tiles'
+            const FileDesc& f = a.files[blockIdx.x];
+            d = const_cast<huff_dcb*>(f.cb);  // the batch builds the codebooks it then reads
+            if (f.status) err = f.status;
+            const uint64_t t0 = f.first, t1 = f.first + (f.n + kEncTile - 1) / kEncTile;
+            uint64_t acc4[4] = {0, 0, 0, 0};
+            uint64_t t = t0;
+            for (; t + 4 <= t1; t += 4)
 #pragma unroll
-            for (int k = 0; k < 4; ++k) acc4[k] += a.tile_hist[(t + k) * 256 + v];
-        for (; t < t1; ++t) acc4[0] += a.tile_hist[t * 256 + v];
-        h = acc4[0] + acc4[1] + acc4[2] + acc4[3];
-        if (f.hist) f.hist[v] = h;
-        if (f.n == 0 && v == 0) {  // an empty file's offset index is [0]
-            f.chunk_off[0] = 0;
-            if (f.sub_lo) f.sub_lo[0] = 0;
-        }
-    } else if (!a.from_lengths) {
-        if (a.acc) {
+                for (int k = 0; k < 4; ++k) acc4[k] += a.tile_hist[(t + k) * 256 + v];
+            for (; t < t1; ++t) acc4[0] += a.tile_hist[t * 256 + v];
+            h = acc4[0] + acc4[1] + acc4[2] + acc4[3];
+            if (f.hist) f.hist[v] = h;
+            if (f.n == 0 && v == 0) {  // an empty file's offset index is [0]
+                f.chunk_off[0] = 0;
+                if (f.sub_lo) f.sub_lo[0] = 0;
+            }
+        } else if (a.acc) {
             for (int c = 0; c < kHistCopies; ++c) {
                 h += a.acc->acc[c][v];
                 a.acc->acc[c][v] = 0;
@@ -477,12 +477,13 @@ hipError_t launch_codebook(const CbArgs& a, uint32_t nblocks, hipStream_t s) {
 // ================================================================= encode
 // Tile offsets.  A tile's code bits are known before it is encoded: from its
 // u16 histogram (sum of count x length, written by k_hist) or, for a
-// standalone encode, counted by k_tile_bits.  The offsets are an exclusive
-// scan of those bits, restarted at every file: k_tile_scan scans inside
-// blocks of kScanTiles tiles, k_blk_scan carries the running total of the
-// file that is open across a block boundary, and a tile's first bit is
+// standalone encode, counted by k_tile_bits.  One stream: k_tile_scan turns
+// them into an exclusive prefix inside blocks of kScanTiles tiles plus one
+// total per block.  A batch: the scan restarts at every file; k_tile_scan_seg
+// scans inside the blocks and k_blk_scan carries the running total of the
+// file that is open across a block boundary, so a tile's first bit is
 // tile_local + (carry of its block if its file began before the block).
-// k_encode reads both one tile ahead and never waits on another workgroup.
+// Either way k_encode never waits on another workgroup.
 constexpr int kScanTiles = kScanTilesPerBlock;
 
 __global__ __launch_bounds__(kEncThreads) void k_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb,
@@ -512,8 +513,47 @@ __global__ __launch_bounds__(kEncThreads) void k_tile_bits(const uint8_t* in, ui
     }
 }
 
-// One workgroup per block of kScanTiles tiles, one thread per tile.
 __global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
+    __shared__ uint32_t s_len[256];
+    __shared__ uint32_t s_wsum[kScanTiles / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (tid < 256) s_len[tid] = a.cb->len[tid];
+    __syncthreads();
+    const uint64_t t = (uint64_t)blockIdx.x * kScanTiles + tid;
+    uint32_t bits = 0;
+    if (t < a.ntiles) {
+        if (a.tile_hist) {
+            const uint4* h = reinterpret_cast<const uint4*>(a.tile_hist + t * 256);
+#pragma unroll 4
+            for (int i = 0; i < 32; ++i) {
+                const uint4 c = h[i];
+                const uint32_t w[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    bits += (w[k] & 0xffffu) * s_len[8 * i + 2 * k];
+                    bits += (w[k] >> 16) * s_len[8 * i + 2 * k + 1];
+                }
+            }
+        } else {
+            bits = a.tile_bits[t];
+        }
+    }
+    const uint32_t incl = wave_incl_scan(bits);
+    if (lane == 63) s_wsum[wave] = incl;
+    __syncthreads();
+    uint32_t before = 0, total = 0;
+    for (int w = 0; w < kScanTiles / 64; ++w) {
+        const uint32_t ws = s_wsum[w];
+        total += ws;
+        before += w < (int)wave ? ws : 0u;
+    }
+    if (t < a.ntiles) a.tile_local[t] = before + incl - bits;
+    if (tid == 0) a.blk_total[blockIdx.x] = total;
+}
+
+// Batch: the same scan restarted at every file.  One workgroup per block of
+// kScanTiles tiles, one thread per tile.
+__global__ __launch_bounds__(kScanTiles) void k_tile_scan_seg(ScanArgs a) {
     __shared__ uint32_t s_len[256];
     __shared__ uint32_t s_wsum[kScanTiles / 64];
     __shared__ uint32_t s_excl[kScanTiles];
@@ -630,7 +670,8 @@ hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, u
 
 hipError_t launch_tile_scan(const ScanArgs& a, hipStream_t s) {
     const uint64_t blocks = (a.ntiles + kScanTiles - 1) / kScanTiles;
-    hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)blocks), dim3(kScanTiles), 0, s, a);
+    if (a.files) hipLaunchKernelGGL(k_tile_scan_seg, dim3((uint32_t)blocks), dim3(kScanTiles), 0, s, a);
+    else hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)blocks), dim3(kScanTiles), 0, s, a);
     return hipGetLastError();
 }
 
@@ -641,11 +682,11 @@ hipError_t launch_blk_scan(const unsigned long long* blk_tail, unsigned long lon
 }
 
 // Persistent encode over 16 KiB tiles (256 threads x 64 bytes); workgroup w
-// takes a contiguous run of tiles and requests the next tile's bytes and
-// offset terms while it encodes the current one.  Each thread packs its 64
-// bytes into a private LDS slot with table lookups; the workgroup scans the
-// per-thread bit counts; the tile's first stream bit is tile_local + carry
-// (two-level tile scan).
+// takes tiles w, w + G, w + 2G, ... and requests the next tile's bytes while
+// it encodes the current one.  Each thread packs its 64 bytes into a private
+// LDS slot with one table lookup per byte; the workgroup scans the
+// per-thread bit counts; the tile's first stream bit is its block prefix
+// plus its offset inside the block.
 //
 // Output words are owned by the thread whose bit range holds the word's last
 // bit; the bits of the owner's first word that precede its range belong to
@@ -653,30 +694,12 @@ hipError_t launch_blk_scan(const unsigned long long* blk_tail, unsigned long lon
 // thread of a tile, are re-derived from the 32 input bytes before the tile.
 // The final partial word of a stream is written by its last thread.  No two
 // threads write the same word.
-//
-// Waits: the vector memory counter retires loads and stores in issue order,
-// and the compiler waits for a load by letting at most the number of memory
-// operations it knows were issued after it stay in flight.  Every thread
-// therefore issues the same, fixed number of stores per tile (buffer stores;
-// a lane with nothing to store gives an offset past the buffer's range, which
-// the hardware drops), so waiting for the prefetched tile never waits for the
-// current tile's stores.
 constexpr int kSlotWords = kEncUnit * 16 / 32 + 1;  // 64 bytes x 16 bits, plus a zero word
 constexpr int kSlotStride = kEncThreads + 1;           // word k of thread t at [k*stride + t]: banks differ along k
 constexpr int kEncWaves = kEncThreads / 64;
-constexpr uint32_t kOff = 0x80000000u;                 // buffer offset that stores nothing
-constexpr uint32_t kRawRsrcFlags = 0x00020000u;        // raw buffer, 32-bit data format
-
-typedef uint32_t v4u32 __attribute__((ext_vector_type(4)));
-typedef uint32_t v2u32 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t byte64(const uint4& a, const uint4& b, const uint4& c, const uint4& d, int i) {
     return i < 16 ? byte_of(a, i) : i < 32 ? byte_of(b, i - 16) : i < 48 ? byte_of(c, i - 32) : byte_of(d, i - 48);
-}
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, uint64_t bytes) {
-    const uint32_t range = bytes < 0x7fffffffull ? (uint32_t)bytes : 0x7fffffffu;
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)range, (int)kRawRsrcFlags);
 }
 
 // Packs one thread's 64 bytes (codes of at most 16 bits) into its LDS slot,
@@ -686,25 +709,25 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_rsrc(const void* base, uin
 // current top word and moves to the next slot word only once that word is
 // full, so there is no branch.  G = 4 reads 8-bit codes from a byte table
 // indexed by the input byte itself.  G = 1 handles a partial unit of nv bytes.
-// A byte without a code (length 0) sets `bad`.
 template <int G>
 __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const uint4 x2, const uint4 x3,
                                           const uint8_t* s_len, const uint8_t* s_code8, const uint16_t* s_code16,
                                           uint32_t* slot, uint32_t& L, uint32_t& nwp, uint32_t& bad,
                                           uint32_t nv = kEncUnit) {
     uint64_t acc = 0;
-    uint32_t na = 0, wi = 0, mn = 255;
+    uint32_t na = 0, wi = 0;
     auto emit = [&]() {
-        const uint32_t sh = __builtin_elementwise_sub_sat(na, 32u);
+        const uint32_t sh = na >= 32 ? na - 32 : 0;
         slot[wi * kSlotStride] = (uint32_t)(acc >> sh);
-        wi += na >> 5;
-        na &= 31u;
+        const uint32_t full = na >= 32 ? 1u : 0u;
+        wi += full;
+        na -= full << 5;
     };
     if constexpr (G == 1) {
         for (uint32_t i = 0; i < nv; ++i) {
             const uint32_t v = byte64(x0, x1, x2, x3, (int)i);
             const uint32_t l = s_len[v];
-            mn = min(mn, l);
+            bad |= l == 0;
             acc = (acc << l) | s_code16[v];
             na += l;
             emit();
@@ -719,7 +742,7 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
                     const uint32_t v = byte64(x0, x1, x2, x3, i0 + k);
                     const uint32_t l = s_len[v];
                     const uint32_t c = G == 4 ? (uint32_t)s_code8[v] : (uint32_t)s_code16[v];
-                    mn = min(mn, l);
+                    bad |= l == 0 ? 1u : 0u;
                     g = (g << l) | c;
                     gl += l;
                 }
@@ -729,7 +752,6 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
             emit();
         }
     }
-    bad |= mn == 0 ? 1u : 0u;
     L = wi * 32 + na;
     nwp = wi;
     if (na) {
@@ -739,171 +761,95 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
     slot[nwp * kSlotStride] = 0;
 }
 
-// Stores a thread's nw output words with a fixed sequence of 3 single-word,
-// M 16-byte and 3 single-word stores.  Output word k is the funnel of slot
-// words k-1 and k (word -1 is `prefix`) at shift sh; `off` is the byte offset
-// of word 0 in `out`, `head` the number of words before the first 16-byte
-// boundary.
-template <int M>
-__device__ __forceinline__ void store_words(__amdgpu_buffer_rsrc_t out, const uint32_t* slot, uint32_t prefix,
-                                            uint32_t sh, uint32_t nw, uint32_t head, uint32_t off) {
-    auto row = [&](int k) -> uint32_t {  // slot word k, k >= -1
-        return k < 0 ? prefix : slot[(uint32_t)min(k, kSlotWords - 1) * kSlotStride];
-    };
-    auto word = [&](int k) -> uint32_t { return __builtin_amdgcn_alignbit(row(k - 1), row(k), sh); };
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-        __builtin_amdgcn_raw_buffer_store_b32(word(k), out, (uint32_t)k < head ? off + 4 * k : kOff, 0, 0);
-    const uint32_t nb = (nw - head) >> 2;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        const int b = (int)head + 4 * m;
-        const uint32_t r0 = row(b - 1), r1 = row(b), r2 = row(b + 1), r3 = row(b + 2), r4 = row(b + 3);
-        v4u32 v = {__builtin_amdgcn_alignbit(r0, r1, sh), __builtin_amdgcn_alignbit(r1, r2, sh),
-                   __builtin_amdgcn_alignbit(r2, r3, sh), __builtin_amdgcn_alignbit(r3, r4, sh)};
-        __builtin_amdgcn_raw_buffer_store_b128(v, out, (uint32_t)m < nb ? off + 4 * (uint32_t)b : kOff, 0, 0);
-    }
-    const uint32_t tb = head + 4 * nb;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-        const uint32_t k = tb + t;
-        __builtin_amdgcn_raw_buffer_store_b32(word((int)k), out, k < nw ? off + 4 * k : kOff, 0, 0);
-    }
-}
-
-constexpr int kWordStores = 3 + 8 + 3;  // stores per thread per tile for the word output, on every path
-
-// `count` stores that store nothing (offset out of range): they pad a path so
-// that every path issues kWordStores word stores.
-template <int count>
-__device__ __forceinline__ void pad_stores(__amdgpu_buffer_rsrc_t out) {
-#pragma unroll
-    for (int i = 0; i < count; ++i) __builtin_amdgcn_raw_buffer_store_b32(0u, out, kOff + 16 * i, 0, 0);  // distinct: not merged
-}
-
-// Waits for every vector memory operation of the wave (loads and stores).
-__device__ __forceinline__ void vmem_drain() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0)
-
-template <bool kBatch, bool kAligned>
+template <bool kBatch>
 __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
     __shared__ uint32_t s_slot[kSlotWords * kSlotStride];  // private slots; tile bytes (generic path)
     __shared__ unsigned long long s_code[256];
     __shared__ uint16_t s_code16[256];
     __shared__ uint8_t s_code8[256];
     __shared__ uint8_t s_len[256];
-    __shared__ uint32_t s_prev4[8];  // the 32 input bytes before the tile
+    __shared__ uint8_t s_prev[32];
     __shared__ uint32_t s_L[kEncThreads];
     __shared__ uint32_t s_wsum[kEncWaves];
-    const uint8_t* s_prev = reinterpret_cast<const uint8_t*>(s_prev4);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const huff_dcb* loaded = nullptr;
     bool fast = true;
     uint32_t group = 1;
+    uint64_t blkDone = 0;           // scan blocks already summed into blkPrefix
+    unsigned long long blkPrefix = 0;
 
     auto fileOf = [&](uint64_t tile) -> const FileDesc& {
         if constexpr (kBatch) return a.files[a.tile_file[tile]];
         else return a.one;
     };
-    // Everything a tile needs from memory is requested one tile ahead (its
-    // bytes, the 32 bytes before it, its offset terms) and used only in the
-    // next iteration.
-    struct Pre {
-        uint4 x0, x1, x2, x3;
-        uint32_t before, local, len;
-        unsigned long long carry, code;
-    };
-    // Tile bytes are prefetched when every input is 16-byte aligned (kAligned),
-    // as whole aligned 16-byte blocks (a block holding a byte of the file lies
-    // in a page the file uses; a block wholly past the end is replaced by
-    // block 0, its bytes are never used).  Otherwise a tile's bytes are read
-    // when it is encoded.  Exactly one load per block, and no conditional
-    // loads or waits in the loop, keep the compiler's wait for the prefetch
-    // precise.
-    auto fetch = [&](uint64_t tile, Pre& p) {
+    auto loadUnit = [&](uint64_t tile, uint4& y0, uint4& y1, uint4& y2, uint4& y3) {
         const FileDesc& d = fileOf(tile);
-        const uint64_t j = tile - d.first;
-        if constexpr (kAligned) {
-            const uint64_t q = j * (uint64_t)kEncTile + (uint64_t)tid * kEncUnit;
-            auto blk = [&](uint64_t at) { return *reinterpret_cast<const uint4*>(d.in + (at < d.n ? at : 0)); };
-            p.x0 = blk(q);
-            p.x1 = blk(q + 16);
-            p.x2 = blk(q + 32);
-            p.x3 = blk(q + 48);
-            // lanes 0..7: the 32 bytes before the tile (a valid dword stands
-            // in when there is nothing before)
-            const uint8_t* bp = j > 0 && tid < 8 ? d.in + j * (uint64_t)kEncTile - 32 + 4 * tid
-                                                 : reinterpret_cast<const uint8_t*>(a.tile_local + tile);
-            p.before = *reinterpret_cast<const uint32_t*>(bp);
-        }
-        // vector loads (a lane index the compiler cannot see is uniform): a
-        // scalar load would share its wait counter with the LDS lookups
-        uint32_t lane0 = (uint32_t)(tid >> 10);
-        asm volatile("" : "+v"(lane0));
-        const uint64_t blk = tile / kScanTiles;
-        // blk_carry[0] is 0: it stands in when the file begins inside the block
-        p.local = a.tile_local[tile + lane0];
-        p.carry = a.blk_carry[(d.first <= blk * kScanTiles ? blk : 0) + lane0];
-        // a new file's codebook entry for this thread's byte value
-        p.code = d.cb->code[tid];
-        p.len = d.cb->len[tid];
+        const uint64_t q = (tile - d.first) * (uint64_t)kEncTile + (uint64_t)tid * kEncUnit;
+        const bool al = ((uintptr_t)d.in & 15u) == 0;
+        y0 = load16(d.in, q, d.n, al);
+        y1 = load16(d.in, q + 16, d.n, al);
+        y2 = load16(d.in, q + 32, d.n, al);
+        y3 = load16(d.in, q + 48, d.n, al);
     };
-
-    const uint64_t per = (a.ntiles + gridDim.x - 1) / gridDim.x;
-    const uint64_t t0 = (uint64_t)blockIdx.x * per;
-    const uint64_t t1 = min<uint64_t>(a.ntiles, t0 + per);
-    Pre cur;
-    cur.x0 = cur.x1 = cur.x2 = cur.x3 = make_uint4(0, 0, 0, 0);
-    cur.before = cur.local = cur.len = 0;
-    cur.carry = cur.code = 0;
-    if (t0 < t1) fetch(t0, cur);
-    // use the prologue's loads here, so that none is pending at the loop head
-    asm volatile("" ::"v"(cur.x0.x), "v"(cur.x0.y), "v"(cur.x0.z), "v"(cur.x0.w), "v"(cur.x1.x), "v"(cur.x1.y),
-                 "v"(cur.x1.z), "v"(cur.x1.w), "v"(cur.x2.x), "v"(cur.x2.y), "v"(cur.x2.z), "v"(cur.x2.w));
-    asm volatile("" ::"v"(cur.x3.x), "v"(cur.x3.y), "v"(cur.x3.z), "v"(cur.x3.w), "v"(cur.before), "v"(cur.local),
-                 "v"(cur.len), "v"(cur.carry), "v"(cur.code));
-    for (uint64_t g = t0; g < t1; ++g) {
+    // A tile's first stream bit: one stream, the sum of the block totals
+    // before its scan block + its offset inside the block; a batch, its
+    // offset inside block and file + the carry of its block when the file
+    // began before the block.  Both are fetched one tile ahead with vector
+    // loads: a scalar load would share its wait counter with the LDS table
+    // lookups and stall them for a memory round trip.
+    auto tileStart = [&](uint64_t tile, uint64_t& done, unsigned long long& prefix) -> uint64_t {
+        const uint64_t blk = tile / kScanTiles;
+        uint32_t lane0 = (uint32_t)(tid >> 10);  // 0, but not known to the compiler: forces vector loads
+        asm volatile("" : "+v"(lane0));
+        if constexpr (kBatch) {
+            const FileDesc& d = fileOf(tile);
+            const unsigned long long carry = d.first <= blk * kScanTiles ? a.blk_carry[blk + lane0] : 0ull;
+            return carry + a.tile_local[tile + lane0];
+        } else {
+            for (; done < blk; ++done) prefix += a.blk_total[done + lane0];
+            return prefix + a.tile_local[tile + lane0];
+        }
+    };
+    uint64_t g = blockIdx.x;
+    uint4 x0 = make_uint4(0, 0, 0, 0), x1 = x0, x2 = x0, x3 = x0;
+    uint64_t Scur = 0;
+    if (g < a.ntiles) {
+        loadUnit(g, x0, x1, x2, x3);
+        Scur = tileStart(g, blkDone, blkPrefix);
+    }
+    for (; g < a.ntiles; g += gridDim.x) {
         const FileDesc& f = fileOf(g);
         const uint64_t j = g - f.first;
         const uint64_t n = f.n;
         const uint64_t tstart = j * (uint64_t)kEncTile;
         const uint64_t q0 = tstart + (uint64_t)tid * kEncUnit;
         const uint32_t nv = q0 >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q0);
-        uint4 x0 = cur.x0, x1 = cur.x1, x2 = cur.x2, x3 = cur.x3;
-        uint32_t prev4 = cur.before;
-        if constexpr (!kAligned) {  // unaligned input: read now
-            x0 = load16(f.in, q0, n, false);
-            x1 = load16(f.in, q0 + 16, n, false);
-            x2 = load16(f.in, q0 + 32, n, false);
-            x3 = load16(f.in, q0 + 48, n, false);
-            prev4 = 0;
-            if (j > 0 && tid < 8) {
-                const uint8_t* bp = f.in + tstart - 32 + 4 * tid;
-                prev4 = (uint32_t)bp[0] | (uint32_t)bp[1] << 8 | (uint32_t)bp[2] << 16 | (uint32_t)bp[3] << 24;
-            }
+        // the next tile's bytes are requested now and used next iteration
+        const uint64_t gn = g + gridDim.x;
+        uint4 y0 = make_uint4(0, 0, 0, 0), y1 = y0, y2 = y0, y3 = y0;
+        uint64_t Snext = 0;
+        if (gn < a.ntiles) {
+            loadUnit(gn, y0, y1, y2, y3);
+            Snext = tileStart(gn, blkDone, blkPrefix);
         }
-        // the tile's first stream bit (the same in every lane: made scalar,
-        // so that the output buffer descriptor is uniform)
-        const uint64_t Sv = cur.carry + cur.local;
-        const uint64_t S = (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)Sv) |
-                           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(Sv >> 32)) << 32;
-        const huff_dcb* cb = f.cb;
-        const uint64_t code = cur.code;
-        const uint32_t len = cur.len;
-        fetch(g + 1 < t1 ? g + 1 : g, cur);  // unconditional: the last tile re-reads itself, unused
-        lds_barrier();  // the previous tile is done with the LDS slots and tables
-        if (tid < 8) s_prev4[tid] = prev4;
-        if (cb != loaded) {
-            const uint32_t maxLen = cb->max_len;
+        __syncthreads();  // the previous tile is done with the LDS slots and tables
+        if (tid < 32 && j > 0) s_prev[tid] = f.in[tstart - 32 + tid];
+        if (f.cb != loaded) {
+            const uint32_t maxLen = f.cb->max_len;
             fast = maxLen <= 16;
             group = maxLen <= 8 ? 4 : maxLen <= 10 ? 3 : 2;  // codes per 32-bit group
-            s_len[tid] = (uint8_t)len;
-            s_code[tid] = code;
-            s_code16[tid] = (uint16_t)code;
-            s_code8[tid] = (uint8_t)code;
-            loaded = cb;
-            lds_barrier();
+            {
+                const uint64_t c = f.cb->code[tid];
+                s_len[tid] = f.cb->len[tid];
+                s_code[tid] = c;
+                s_code16[tid] = (uint16_t)c;
+                s_code8[tid] = (uint8_t)c;
+            }
+            loaded = f.cb;
+            __syncthreads();
         }
+        const uint64_t S = Scur;  // the tile's first stream bit
 
         // 1) pack into the private slot (fast) or count bits (generic)
         uint32_t L = 0, nwp = 0, bad = 0;
@@ -945,7 +891,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
         s_L[tid] = L;
         const uint32_t incl = wave_incl_scan(L);
         if (lane == 63) s_wsum[wave] = incl;
-        lds_barrier();
+        __syncthreads();
         uint32_t before = 0, agg = 0;
 #pragma unroll
         for (int w = 0; w < kEncWaves; ++w) {
@@ -957,37 +903,21 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
         const uint32_t sh = (uint32_t)(b & 31);
         const bool lastThread = nv > 0 && q0 + kEncUnit >= n;
 
-        // 3) segment index and decode index: one buffer store each, so that
-        // every thread issues the same number of stores
-        {
-            const uint64_t c0 = tstart >> a.chunk_log2;  // first chunk entry of this tile
-            const uint64_t nch = ((n + (1ull << a.chunk_log2) - 1) >> a.chunk_log2) + 1;
-            const bool atChunk = nv && (q0 & ((1ull << a.chunk_log2) - 1)) == 0;
-            const v2u32 bv = {(uint32_t)b, (uint32_t)(b >> 32)};
-            __builtin_amdgcn_raw_buffer_store_b64(
-                bv, raw_rsrc(f.chunk_off + c0, (nch - c0) * 8),
-                atChunk ? (uint32_t)(((q0 >> a.chunk_log2) - c0) * 8) : kOff, 0, 0);
-        }
-        if (a.sub_log2 == kNoSub) {
-            __builtin_amdgcn_raw_buffer_store_b32(0u, raw_rsrc(f.chunk_off, 8), kOff, 0, 0);  // same count
-        } else {
-            if (a.sub_log2 >= 6) {
-                const uint64_t s0 = tstart >> a.sub_log2;
-                const uint64_t nsb = ((n + (1ull << a.sub_log2) - 1) >> a.sub_log2) + 1;
-                const bool atSub = nv && (q0 & ((1ull << a.sub_log2) - 1)) == 0;
-                __builtin_amdgcn_raw_buffer_store_b32(
-                    (uint32_t)b, raw_rsrc(f.sub_lo + s0, (nsb - s0) * 4),
-                    atSub ? (uint32_t)(((q0 >> a.sub_log2) - s0) * 4) : kOff, 0, 0);
-            } else if (nv) {
-                // sub-blocks of 16 or 32 bytes: bit offsets inside the unit
-                const uint32_t step = 1u << a.sub_log2;
-                uint32_t run = 0;
-                for (uint32_t at = 0; at < nv; at += step) {
-                    f.sub_lo[(q0 + at) >> a.sub_log2] = (uint32_t)(b + run);
-                    for (uint32_t i = at; i < at + step && i < nv; ++i) run += s_len[byte64(x0, x1, x2, x3, (int)i)];
+        // 3) segment index and decode index
+        if (nv) {
+            if ((q0 & ((1ull << a.chunk_log2) - 1)) == 0) f.chunk_off[q0 >> a.chunk_log2] = b;
+            if (a.sub_log2 != kNoSub) {
+                if (a.sub_log2 >= 6) {
+                    if ((q0 & ((1ull << a.sub_log2) - 1)) == 0) f.sub_lo[q0 >> a.sub_log2] = (uint32_t)b;
+                } else {
+                    // sub-blocks of 16 or 32 bytes: bit offsets inside the unit
+                    const uint32_t step = 1u << a.sub_log2;
+                    uint32_t run = 0;
+                    for (uint32_t at = 0; at < nv; at += step) {
+                        f.sub_lo[(q0 + at) >> a.sub_log2] = (uint32_t)(b + run);
+                        for (uint32_t i = at; i < at + step && i < nv; ++i) run += s_len[byte64(x0, x1, x2, x3, (int)i)];
+                    }
                 }
-            } else {
-                __builtin_amdgcn_raw_buffer_store_b32(0u, raw_rsrc(f.chunk_off, 8), kOff, 0, 0);  // same count
             }
         }
         if (lastThread) {
@@ -1022,33 +952,42 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
         // 5) write the owned words
         const uint64_t w0 = b >> 5;
         const uint64_t tileEnd = S + agg;
+        const bool tileLast = tstart + kEncTile >= n;
         const bool capOK = ((tileEnd + 31) >> 5) <= f.nwords;  // the whole tile fits
         if (fast) {
-            uint32_t nw = nv ? (uint32_t)((e >> 5) - w0) : 0u;
+            uint32_t nw = (uint32_t)((e >> 5) - w0);
             if (lastThread && (e & 31)) ++nw;
+            uint32_t* wp = f.words + w0;
             const uint32_t* slot = s_slot + tid;
+            uint32_t prevw = prefix;
             if (capOK) {
-                const uint64_t tw = S >> 5;  // the tile's first word
-                const __amdgpu_buffer_rsrc_t out = raw_rsrc(f.words + tw, (f.nwords - tw) * 4);
-                const uint32_t off = (uint32_t)(w0 - tw) * 4;
-                const uint32_t head = min(nw, ((uint32_t)(0u - (uint32_t)(uintptr_t)(f.words + w0)) & 15u) >> 2);
-                if (group == 4) {
-                    store_words<4>(out, slot, prefix, sh, nw, head, off);
-                    pad_stores<kWordStores - 10>(out);
-                } else if (group == 3) {
-                    store_words<5>(out, slot, prefix, sh, nw, head, off);
-                    pad_stores<kWordStores - 11>(out);
-                } else {
-                    store_words<8>(out, slot, prefix, sh, nw, head, off);
-                }
-            } else {
-                uint32_t prevw = prefix;
-                for (uint32_t k = 0; k < nw; ++k) {
+                // single words up to a 16-byte boundary, then 16-byte stores
+                uint32_t k = 0;
+                const uint32_t head = min(nw, ((uint32_t)(0u - (uint32_t)(uintptr_t)wp) & 15u) >> 2);
+                for (; k < head; ++k) {
                     const uint32_t cur = slot[k * kSlotStride];
-                    if (w0 + k < f.nwords) f.words[w0 + k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
+                    wp[k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
                     prevw = cur;
                 }
-                pad_stores<kWordStores>(raw_rsrc(f.words, 4));
+                for (; k + 4 <= nw; k += 4) {
+                    const uint32_t c0 = slot[k * kSlotStride], c1 = slot[(k + 1) * kSlotStride];
+                    const uint32_t c2 = slot[(k + 2) * kSlotStride], c3 = slot[(k + 3) * kSlotStride];
+                    *reinterpret_cast<uint4*>(wp + k) =
+                        make_uint4(__builtin_amdgcn_alignbit(prevw, c0, sh), __builtin_amdgcn_alignbit(c0, c1, sh),
+                                   __builtin_amdgcn_alignbit(c1, c2, sh), __builtin_amdgcn_alignbit(c2, c3, sh));
+                    prevw = c3;
+                }
+                for (; k < nw; ++k) {
+                    const uint32_t cur = slot[k * kSlotStride];
+                    wp[k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
+                    prevw = cur;
+                }
+            } else {
+                for (uint32_t k = 0; k < nw; ++k) {
+                    const uint32_t cur = slot[k * kSlotStride];
+                    if (w0 + k < f.nwords) wp[k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
+                    prevw = cur;
+                }
             }
         } else if (nv) {
             uint64_t acc = prefix;
@@ -1076,21 +1015,18 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
             }
             if (lastThread && na && w < f.nwords) f.words[w] = (uint32_t)(acc << (32 - na));
         }
-        if (!fast) pad_stores<kWordStores>(raw_rsrc(f.words, 4));
+        x0 = y0;
+        x1 = y1;
+        x2 = y2;
+        x3 = y3;
+        Scur = Snext;
     }
 }
 
 hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s) {
-    if (a.files) {
-        if (a.aligned) hipLaunchKernelGGL((k_encode<true, true>), dim3(grid), dim3(kEncThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_encode<true, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
-    } else {
-        if (a.aligned) hipLaunchKernelGGL((k_encode<false, true>), dim3(grid), dim3(kEncThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_encode<false, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
-    }
+    if (a.files) hipLaunchKernelGGL(k_encode<true>, dim3(grid), dim3(kEncThreads), 0, s, a);
+    else hipLaunchKernelGGL(k_encode<false>, dim3(grid), dim3(kEncThreads), 0, s, a);
     return hipGetLastError();
-
-
 }
 
 __global__ void k_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo) {

@@ -29,9 +29,9 @@ struct huff_ctx {
 // (slices of its arena).
 struct huff_batch {
     huff_ctx* ctx = nullptr;
+    int device = 0;              // ctx's device (destroy may run after the context is gone)
     uint32_t nfiles = 0, chunk_size = 0, sub_size = 0;
     uint64_t ntiles = 0, nitems = 0;
-    bool aligned = true;     // every input 16-byte aligned
     huff::FileDesc* d_enc = nullptr;   // [nfiles], first = first tile
     huff::FileDesc* d_dec = nullptr;   // [nfiles], first = first decode lane (256-aligned)
     uint32_t* d_tile_file = nullptr;
@@ -46,7 +46,6 @@ struct huff_batch {
 };
 
 namespace huff {
-
 
 struct DeviceGuard {
     int prev = -1;
@@ -76,7 +75,6 @@ struct BatchTables {
     std::vector<FileDesc> dec;       // first = first decode lane (kDecBatchBlock-aligned)
     std::vector<uint32_t> tile_file; // tile -> file
     uint64_t ntiles = 0, nitems = 0;
-    bool aligned = true;
 };
 
 // Validates `files` and fills `t`.  HUFF_E_INVAL on a bad file or sizes.

@@ -315,40 +315,40 @@ bool huff_server::launch(Slot& sl) {
     if (st == HUFF_OK) st = batch_tables(df.data(), (uint32_t)df.size(), cfg.chunk_size, cfg.sub_size, dt, true);
     // staging: [enc | dec | status zeros | length pointers | tile_file]
     const uint64_t sz_enc = cf.size() * sizeof(FileDesc), sz_dec = df.size() * sizeof(FileDesc);
-    const uint64_t need = sz_enc + sz_dec + nreq * 4 + cf.size() * 8 + ct.ntiles * 4;
+    const uint64_t o_stat = sz_enc + sz_dec, o_lp = o_stat + up(nreq * 4, 8), o_tf = o_lp + cf.size() * 8;
+    const uint64_t need = o_tf + ct.ntiles * 4;
     if (st == HUFF_OK && !grow_pinned(sl.staging, sl.staging_bytes, need)) st = HUFF_E_NOMEM;
     if (st == HUFF_OK && !grow_pinned(sl.readback, sl.readback_bytes, nreq * 4 + cf.size() * 8 + 16)) st = HUFF_E_NOMEM;
     if (st == HUFF_OK) {
         uint8_t* h = (uint8_t*)sl.staging;
         memcpy(h, ct.enc.data(), sz_enc);
         memcpy(h + sz_enc, dt.dec.data(), sz_dec);
-        memset(h + sz_enc + sz_dec, 0, nreq * 4);
-        const uint64_t** lp = (const uint64_t**)(h + sz_enc + sz_dec + nreq * 4);
+        memset(h + o_stat, 0, nreq * 4);
+        const uint64_t** lp = (const uint64_t**)(h + o_lp);
         for (size_t i = 0; i < cf.size(); ++i) {
             const uint64_t nch = (cf[i].n + cfg.chunk_size - 1) / cfg.chunk_size;
             lp[i] = cf[i].chunk_off + nch;
         }
-        memcpy(h + sz_enc + sz_dec + nreq * 4 + cf.size() * 8, ct.tile_file.data(), ct.ntiles * 4);
+        memcpy(h + o_tf, ct.tile_file.data(), ct.ntiles * 4);
         hipStream_t s = sl.stream;
         bool ok = true;
         if (sz_enc) ok = ok && hipMemcpyAsync(d_enc, h, sz_enc, hipMemcpyHostToDevice, s) == hipSuccess;
         if (sz_dec) ok = ok && hipMemcpyAsync(d_dec, h + sz_enc, sz_dec, hipMemcpyHostToDevice, s) == hipSuccess;
-        ok = ok && hipMemcpyAsync(d_status, h + sz_enc + sz_dec, nreq * 4, hipMemcpyHostToDevice, s) == hipSuccess;
+        ok = ok && hipMemcpyAsync(d_status, h + o_stat, nreq * 4, hipMemcpyHostToDevice, s) == hipSuccess;
         if (cf.size())
             ok = ok && hipMemcpyAsync(d_lenptr, lp, cf.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess;
         if (ct.ntiles)
-            ok = ok && hipMemcpyAsync(d_tile_file, h + sz_enc + sz_dec + nreq * 4 + cf.size() * 8, ct.ntiles * 4,
-                                      hipMemcpyHostToDevice, s) == hipSuccess;
+            ok = ok && hipMemcpyAsync(d_tile_file, h + o_tf, ct.ntiles * 4, hipMemcpyHostToDevice, s) == hipSuccess;
         if (!ok) st = HUFF_E_HIP;
         // the two plans over the tables block
         huff_batch pc, pd;
         pc.ctx = pd.ctx = ctx;
+        pc.device = pd.device = ctx->device;
         pc.owns = pd.owns = false;
         pc.chunk_size = pd.chunk_size = cfg.chunk_size;
         pc.sub_size = pd.sub_size = cfg.sub_size;
         pc.nfiles = (uint32_t)cf.size();
         pc.ntiles = ct.ntiles;
-        pc.aligned = ct.aligned;
         pc.d_enc = d_enc;
         pc.d_tile_file = d_tile_file;
         const uint64_t nblk = ct.ntiles / kScanTilesPerBlock + 1;

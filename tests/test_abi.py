@@ -40,6 +40,10 @@ def test_struct_sizes_match_c():
     assert lib.huff_abi_sizeof(0) == ctypes.sizeof(_abi.HuffDcb)
     assert lib.huff_abi_sizeof(1) == ctypes.sizeof(_abi.HuffCodebook)
     assert lib.huff_abi_sizeof(2) == ctypes.sizeof(_abi.HuffParams)
+    for i, cls in enumerate((_abi.HuffFile, _abi.HuffServerCfg, _abi.HuffRequest, _abi.HuffResult,
+                             _abi.HuffStreamInfo), start=3):
+        assert lib.huff_abi_sizeof(i) == ctypes.sizeof(cls), cls.__name__
+    assert lib.huff_abi_sizeof(99) == 0
 
 
 def test_strerror():
@@ -56,6 +60,34 @@ def test_invalid_arguments_rejected_without_device():
     assert lib.huff_build_codebook(None, None) == _abi.HUFF_E_INVAL
     out = ctypes.c_void_p()
     assert lib.huff_ctx_create(-1, None, ctypes.byref(out)) == _abi.HUFF_E_INVAL
+
+
+def test_batch_and_server_reject_null_handles_without_device():
+    lib = P.load()
+    INVAL = _abi.HUFF_E_INVAL
+    out = ctypes.c_void_p()
+    f = (_abi.HuffFile * 1)()
+    assert lib.huff_batch_create(None, f, 1, 1024, 0, ctypes.byref(out)) == INVAL
+    assert lib.huff_batch_create(None, f, 1, 1024, 0, None) == INVAL
+    assert lib.huff_batch_run(None, 0, 0, None) == INVAL
+    assert lib.huff_compress_batch(None, None) == INVAL
+    assert lib.huff_encode_batch(None, None) == INVAL
+    assert lib.huff_decode_batch(None, None) == INVAL
+    lib.huff_batch_destroy(None)
+    cfg = _abi.HuffServerCfg(1 << 20, 2, 16, 1 << 16, 0)
+    assert lib.huff_server_create(None, ctypes.byref(cfg), ctypes.byref(out)) == INVAL
+    req = _abi.HuffRequest(0, 0, None, 0, 0)
+    t = ctypes.c_uint64()
+    r = _abi.HuffResult()
+    assert lib.huff_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == INVAL
+    assert lib.huff_server_poll(None, 1, ctypes.byref(r)) == INVAL
+    assert lib.huff_server_wait(None, 1, ctypes.byref(r)) == INVAL
+    assert lib.huff_server_stream(None, 1, None) == INVAL
+    assert lib.huff_server_release(None, 1) == INVAL
+    assert lib.huff_server_replay(None, None, None, 0, None) == INVAL
+    st = (ctypes.c_uint64 * 6)()
+    assert lib.huff_server_stats(None, st) == INVAL
+    lib.huff_server_destroy(None)
 
 
 def _hist_cases():
