@@ -16,6 +16,7 @@ import json
 import os
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -29,7 +30,10 @@ WORKLOADS = {
     "markov_2GiB": ("2 GiB order-2 Markov text, 1 MiB chunks", 1 << 20, 256),
     "zipf256_2GiB": ("2 GiB i.i.d. Zipf(0.8) over 256 byte values, 1 MiB chunks", 1 << 20, 256),
 }
-KERNELS = {"compress": "k_hist+k_codebook+k_encode", "decode": "k_decode_staged"}
+# kernel ids of huff_ctx_kernel_time -> kernel names (decode: the staged kernel
+# for sub-blocks of 32..256 bytes, the direct one otherwise)
+KERNEL_NAMES = {"hist": "k_hist", "codebook": "k_codebook", "scan": "k_tile_scan", "encode": "k_encode",
+                "decode": "k_decode_staged"}
 
 
 def kernel_source_hash() -> str:
@@ -82,7 +86,8 @@ def batch_leg(P, codec, nfiles: int, reps: int):
     import datagen
 
     t0 = time.perf_counter()
-    data = [datagen.batch_file(5, i) for i in range(nfiles)]
+    with ThreadPoolExecutor(16) as ex:  # one file per task: most files are a single generator block
+        data = list(ex.map(lambda i: datagen.batch_file(5, i), range(nfiles)))
     total = sum(a.size for a in data)
     xs = [torch.from_numpy(a).cuda() for a in data]
     chunk, sub = 256 << 10, 256
@@ -298,6 +303,16 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
+    # per-kernel launch durations: the same steps again, with the library
+    # recording a HIP event pair around each launch on the stream the kernel
+    # runs on (kept out of the pass above: each event adds a few us between
+    # launches)
+    codec.set_timing(True)
+    for k in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    ktime = {k: codec.kernel_time(k) for k in KERNEL_NAMES}
+    codec.set_timing(False)
 
     assert int(status.item()) == 0, f"device status {int(status.item())}"
     assert torch.equal(out, x), "decoded output differs from the input"
@@ -313,10 +328,27 @@ def main():
         "compress": 2 * n + T / 8 + index_bytes + P.DCB_BYTES,
         "decode": T / 8 + n + index_bytes,
     }
-    dom = max(alg, key=lambda p: phase_ms[p])
-    achieved = alg[dom] / (phase_ms[dom] * 1e-3) / 1e9
+    ntiles = (n + (16 << 10) - 1) // (16 << 10)
+    kalg = {  # algorithmic HBM bytes per launch of each kernel
+        "hist": n,
+        "codebook": P.DCB_BYTES,
+        "scan": ntiles * (512 + 4),  # u16 tile histograms in, tile offsets out
+        "encode": n + T / 8 + index_bytes,  # input in; words, segment and decode index out
+        "decode": T / 8 + index_bytes + n,  # words and index in; bytes out
+    }
+    names = dict(KERNEL_NAMES)
+    if not (sub and 32 <= sub <= 256):
+        names["decode"] = "k_decode"
+    kernels = {}
+    for k, (ms, cnt) in ktime.items():
+        avg = ms / max(1, cnt)
+        kernels[names[k]] = {"launches": cnt, "avg_us": round(avg * 1e3, 2),
+                             "alg_GBps": round(kalg[k] / (avg * 1e-3) / 1e9, 1) if cnt else None}
+    dom = max(ktime, key=lambda k: ktime[k][0])  # largest share of the step
+    avg_ms = ktime[dom][0] / max(1, ktime[dom][1])
+    achieved = kalg[dom] / (avg_ms * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = read_traffic(args.workload, KERNELS[dom], src_hash)
+    traffic = read_traffic(args.workload, names[dom], src_hash)
 
     value = n * args.steps / wall / 1e9
     line = {
@@ -337,9 +369,12 @@ def main():
                    "step": "huff_compress (histogram + device codebook + encode) + huff_decode"},
         "phases": {p: {"ms": round(phase_ms[p], 4), "alg_GBps": round(alg[p] / (phase_ms[p] * 1e-3) / 1e9, 1)}
                    for p in phase_ms},
-        "roofline": {"bound": "hbm", "kernel": KERNELS[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+        "roofline": {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic)},
+                     "traffic": None if traffic is None else round(traffic),
+                     "alg_bytes_per_launch": round(kalg[dom]), "avg_launch_us": round(avg_ms * 1e3, 2),
+                     "kernel_source_sha256": src_hash},
+        "kernels": kernels,
     }
     if not args.no_cpu:
         passes = args.cpu_passes

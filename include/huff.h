@@ -126,6 +126,28 @@ huff_status huff_ctx_get_params(const huff_ctx* ctx, huff_params* out);
 huff_status huff_ctx_status(huff_ctx* ctx, int32_t* out, int reset);
 
 /*
+ * Kernel timing (measurement support, not part of the method).  While timing
+ * is on, the single-stream calls (huff_histogram, huff_compress, huff_encode,
+ * huff_decode and the device codebook builds) record a HIP event before and
+ * after each launch of the kernels below, on the stream the kernel runs on;
+ * batch plans and the server record nothing.  huff_ctx_kernel_time waits for
+ * the recorded events and returns the summed launch durations (ms) and the
+ * launch count of one kernel since the last reset; reset != 0 clears that
+ * kernel's record.  Turning timing off drops unread records.  Launches
+ * queued on a stream that is being captured into a graph are not recorded.
+ */
+enum {
+    HUFF_K_HIST = 0,      /* k_hist: byte histogram */
+    HUFF_K_CODEBOOK = 1,  /* k_codebook: lengths, canonical codes, decode tables */
+    HUFF_K_SCAN = 2,      /* k_tile_bits + k_tile_scan: tile offsets */
+    HUFF_K_ENCODE = 3,    /* k_encode: packing, segment and decode index */
+    HUFF_K_DECODE = 4,    /* k_decode_staged or k_decode */
+    HUFF_K_COUNT = 5
+};
+huff_status huff_ctx_set_timing(huff_ctx* ctx, int enable);
+huff_status huff_ctx_kernel_time(huff_ctx* ctx, int kernel, double* total_ms, uint64_t* launches, int reset);
+
+/*
  * Byte histogram (Method 1's frequency count): d_hist[v] = number of i < n
  * with d_in[i] == v, as 256 u64.  d_in has any alignment.
  */
@@ -192,7 +214,8 @@ huff_status huff_compress(huff_ctx* ctx, const uint8_t* d_in, uint64_t n, uint32
  * every sub_size input bytes, otherwise one lane per chunk.  A code that is
  * not in d_cb, or a chunk / sub-block whose last code does not end exactly at
  * the next index entry, is reported as HUFF_E_CORRUPT (the bytes of that
- * sub-block are then unspecified).
+ * sub-block are then unspecified).  d_out has any alignment; 16-byte aligned
+ * is the fast path.
  */
 huff_status huff_decode(huff_ctx* ctx, const uint32_t* d_words, uint64_t nwords, const uint64_t* d_chunk_off,
                         uint64_t n, uint32_t chunk_size, const uint32_t* d_sub_lo, uint32_t sub_size,
@@ -220,7 +243,7 @@ typedef struct huff_file {
     uint64_t cap_words;  /* capacity of words (encode) / words valid (decode) */
     uint64_t* chunk_off; /* device: nchunks + 1 segment offsets */
     uint32_t* sub_lo;    /* device: nsub + 1 decode-index entries, or NULL when the batch has no sub index */
-    uint8_t* out;        /* device: decode output (n bytes), or NULL if the batch is never decoded */
+    uint8_t* out;        /* device: decode output (n bytes, 16-byte aligned), or NULL if the batch is never decoded */
     uint64_t* hist;      /* device: 256-entry histogram written by compress, or NULL */
     int32_t* status;     /* device: the file's status word, or NULL for the context's */
 } huff_file;
@@ -251,6 +274,8 @@ void huff_batch_destroy(huff_batch* batch);
  * use_graph != 0 the launch sequence of this operation is captured into a
  * HIP graph on first use and replayed afterwards (the files' buffers must
  * then stay the same).  Errors found on the device go to files[i].status.
+ * HUFF_OP_DECODE on a plan where a non-empty file has no `out` returns
+ * HUFF_E_INVAL.
  */
 huff_status huff_batch_run(huff_batch* batch, int op, int use_graph, void* stream);
 

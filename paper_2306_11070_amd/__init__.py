@@ -13,6 +13,7 @@ import os
 
 import numpy as np
 
+from . import _abi
 from ._abi import (HuffCodebook, HuffDcb, HuffFile, HuffParams, HuffRequest, HuffResult, HuffServerCfg,
                    HuffStreamInfo, ERRORS, HuffError, lib, load, HUFF_OP_COMPRESS, HUFF_OP_ENCODE, HUFF_OP_DECODE,
                    HUFF_E_AGAIN)
@@ -82,6 +83,19 @@ class Codec:
             self.close()
         except Exception:
             pass
+
+    def set_timing(self, enable: bool = True):
+        """huff_ctx_set_timing: record HIP events around this context's kernel
+        launches (single-stream calls only)."""
+        _check(lib().huff_ctx_set_timing(self._ctx, 1 if enable else 0), "huff_ctx_set_timing")
+
+    def kernel_time(self, kernel: str, reset: bool = True) -> tuple[float, int]:
+        """huff_ctx_kernel_time: (summed launch ms, launches) of one kernel
+        ('hist', 'codebook', 'scan', 'encode' or 'decode')."""
+        ms, k = ctypes.c_double(), ctypes.c_uint64()
+        _check(lib().huff_ctx_kernel_time(self._ctx, _abi.KERNEL_IDS[kernel], ctypes.byref(ms), ctypes.byref(k),
+                                          1 if reset else 0), "huff_ctx_kernel_time")
+        return float(ms.value), int(k.value)
 
     # -- helpers -------------------------------------------------------------
     def _stream(self, stream):

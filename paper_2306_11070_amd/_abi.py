@@ -11,6 +11,9 @@ ERRORS = {0: "HUFF_OK", -1: "HUFF_E_INVAL", -2: "HUFF_E_CAPACITY", -3: "HUFF_E_C
           -5: "HUFF_E_AGAIN", -6: "HUFF_E_HIP", -7: "HUFF_E_CODELEN", -8: "HUFF_E_NOTFOUND"}
 HUFF_OK, HUFF_E_INVAL, HUFF_E_CAPACITY, HUFF_E_CORRUPT, HUFF_E_NOMEM = 0, -1, -2, -3, -4
 HUFF_E_AGAIN, HUFF_E_HIP, HUFF_E_CODELEN, HUFF_E_NOTFOUND = -5, -6, -7, -8
+#: kernel ids of huff_ctx_kernel_time
+HUFF_K_HIST, HUFF_K_CODEBOOK, HUFF_K_SCAN, HUFF_K_ENCODE, HUFF_K_DECODE = 0, 1, 2, 3, 4
+KERNEL_IDS = {"hist": 0, "codebook": 1, "scan": 2, "encode": 3, "decode": 4}
 
 
 class HuffError(RuntimeError):
@@ -79,6 +82,8 @@ PROTOTYPES = {
     "huff_ctx_set_params": (_i32, [_vp, _vp]),
     "huff_ctx_get_params": (_i32, [_vp, _vp]),
     "huff_ctx_status": (_i32, [_vp, _vp, _int]),
+    "huff_ctx_set_timing": (_i32, [_vp, _int]),
+    "huff_ctx_kernel_time": (_i32, [_vp, _int, _vp, _vp, _int]),
     "huff_histogram": (_i32, [_vp, _vp, _u64, _vp, _vp]),
     "huff_build_codebook": (_i32, [_vp, _vp]),
     "huff_encoded_bits": (_u64, [_vp, _vp]),

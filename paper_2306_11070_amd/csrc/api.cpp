@@ -65,6 +65,59 @@ huff_status ensure_tiles(huff_ctx* ctx, uint64_t tiles) {
     return HUFF_OK;
 }
 
+// Event pair around the launches made during its lifetime, kept per kernel
+// id while the context's timing is on (huff_ctx_set_timing).  A stream being
+// captured into a graph records nothing.
+hipEvent_t take_event(huff_ctx* c) {
+    if (!c->spare_events.empty()) {
+        hipEvent_t e = c->spare_events.back();
+        c->spare_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
+
+class KernelTimer {
+public:
+    KernelTimer(huff_ctx* c, int kernel, hipStream_t s) : c_(c), k_(kernel), s_(s) {
+        if (!c_->timing) return;
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s_, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return;
+        a_ = take_event(c_);
+        if (a_ && hipEventRecord(a_, s_) != hipSuccess) {
+            c_->spare_events.push_back(a_);
+            a_ = nullptr;
+        }
+    }
+    ~KernelTimer() {
+        if (!a_) return;
+        hipEvent_t b = take_event(c_);
+        if (b && hipEventRecord(b, s_) == hipSuccess) {
+            c_->spans[k_].push_back({a_, b});
+            return;
+        }
+        c_->spare_events.push_back(a_);
+        if (b) c_->spare_events.push_back(b);
+    }
+    KernelTimer(const KernelTimer&) = delete;
+    KernelTimer& operator=(const KernelTimer&) = delete;
+
+private:
+    huff_ctx* c_;
+    int k_;
+    hipStream_t s_;
+    hipEvent_t a_ = nullptr;
+};
+
+void drop_spans(huff_ctx* c, int k) {
+    for (auto& p : c->spans[k]) {
+        c->spare_events.push_back(p.first);
+        c->spare_events.push_back(p.second);
+    }
+    c->spans[k].clear();
+}
+
 }  // namespace
 
 extern "C" {
@@ -122,6 +175,8 @@ void huff_ctx_destroy(huff_ctx* c) {
     (void)hipFree(c->blk_tail);
     (void)hipFree(c->blk_carry);
     if (c->status) (void)hipFree(c->status);
+    for (int k = 0; k < HUFF_K_COUNT; ++k) drop_spans(c, k);
+    for (hipEvent_t e : c->spare_events) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -134,6 +189,31 @@ huff_status huff_ctx_set_params(huff_ctx* c, const huff_params* p) {
 huff_status huff_ctx_get_params(const huff_ctx* c, huff_params* out) {
     if (!c || !out) return HUFF_E_INVAL;
     *out = c->params;
+    return HUFF_OK;
+}
+
+huff_status huff_ctx_set_timing(huff_ctx* c, int enable) {
+    if (!c) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    if (!enable)
+        for (int k = 0; k < HUFF_K_COUNT; ++k) drop_spans(c, k);
+    c->timing = enable != 0;
+    return HUFF_OK;
+}
+
+huff_status huff_ctx_kernel_time(huff_ctx* c, int kernel, double* total_ms, uint64_t* launches, int reset) {
+    if (!c || kernel < 0 || kernel >= HUFF_K_COUNT || !total_ms || !launches) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    double sum = 0.0;
+    for (auto& p : c->spans[kernel]) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second) != hipSuccess || hipEventElapsedTime(&ms, p.first, p.second) != hipSuccess)
+            return HUFF_E_HIP;
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = c->spans[kernel].size();
+    if (reset) drop_spans(c, kernel);
     return HUFF_OK;
 }
 
@@ -162,6 +242,7 @@ huff_status launch_hist_only(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint1
     a.tile_hist = tile_hist;
     a.depth_log2 = log2u(c->params.hist_depth);
     a.tiles_per_block = tpb;
+    KernelTimer kt(c, HUFF_K_HIST, s);
     return hip_status(launch_histogram(a, (uint32_t)blocks, s));
 }
 
@@ -181,22 +262,36 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
                               uint32_t* d_sub_lo, int32_t* d_status, bool from_hist, hipStream_t s) {
     if (n == 0) return hip_status(launch_encode_empty(d_chunk_off, sub_size ? d_sub_lo : nullptr, s));
     const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
-    huff_status st;
+    huff_status st = HUFF_OK;
     if (!from_hist) {
         st = ensure_tiles(c, ntiles);
         if (st != HUFF_OK) return st;
-        st = hip_status(launch_tile_bits(d_in, n, d_cb, c->tile_bits, s));
-        if (st != HUFF_OK) return st;
     }
-    ScanArgs sa;
-    memset(&sa, 0, sizeof(sa));
-    sa.tile_hist = from_hist ? c->tile_hist : nullptr;
-    sa.tile_bits = from_hist ? nullptr : c->tile_bits;
-    sa.cb = d_cb;
-    sa.ntiles = ntiles;
-    sa.tile_local = c->tile_local;
-    sa.blk_total = c->blk_tail;  // one stream: the block-tail buffer holds block totals
-    st = hip_status(launch_tile_scan(sa, s));
+    {
+        // code bits per tile (from the tile histograms, or counted from the
+        // input), then their scan
+        KernelTimer kt(c, HUFF_K_SCAN, s);
+        if (from_hist) {
+            TileBitsArgs ta;
+            memset(&ta, 0, sizeof(ta));
+            ta.tile_hist = c->tile_hist;
+            ta.cb = d_cb;
+            ta.ntiles = ntiles;
+            ta.tile_bits = c->tile_bits;
+            st = hip_status(launch_tile_bits_hist(ta, s));
+        } else {
+            st = hip_status(launch_tile_bits(d_in, n, d_cb, c->tile_bits, s));
+        }
+        if (st == HUFF_OK) {
+            ScanArgs sa;
+            memset(&sa, 0, sizeof(sa));
+            sa.tile_bits = c->tile_bits;
+            sa.ntiles = ntiles;
+            sa.tile_local = c->tile_local;
+            sa.blk_total = c->blk_tail;  // one stream: the block-tail buffer holds block totals
+            st = hip_status(launch_tile_scan(sa, s));
+        }
+    }
     if (st != HUFF_OK) return st;
     EncArgs a;
     memset(&a, 0, sizeof(a));
@@ -218,6 +313,7 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
     a.blk_total = c->blk_tail;
     a.err = c->status;
     const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)c->num_cus * c->params.enc_blocks_per_cu);
+    KernelTimer kt(c, HUFF_K_ENCODE, s);
     return hip_status(launch_encode(a, (uint32_t)grid, s));
 }
 }  // namespace
@@ -307,6 +403,7 @@ huff_status huff_build_codebook_device(huff_ctx* c, const uint64_t* d_hist, huff
     a.out = d_cb;
     a.err = d_status ? d_status : c->status;
     a.from_lengths = 0;
+    KernelTimer kt(c, HUFF_K_CODEBOOK, as_stream(stream));
     return hip_status(launch_codebook(a, 1, as_stream(stream)));
 }
 
@@ -327,6 +424,7 @@ huff_status huff_codebook_upload(huff_ctx* c, const huff_codebook* cb, huff_dcb*
     a.err = c->status;
     a.from_lengths = 1;
     memcpy(a.len, cb->len, 256);
+    KernelTimer kt(c, HUFF_K_CODEBOOK, as_stream(stream));
     return hip_status(launch_codebook(a, 1, as_stream(stream)));
 }
 
@@ -361,7 +459,10 @@ huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t
     a.hist_out = d_hist;
     a.out = d_cb;
     a.err = d_status ? d_status : c->status;
-    st = hip_status(launch_codebook(a, 1, s));
+    {
+        KernelTimer kt(c, HUFF_K_CODEBOOK, s);
+        st = hip_status(launch_codebook(a, 1, s));
+    }
     if (st != HUFF_OK) return st;
     return launch_encode_one(c, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
                              d_status, true, s);
@@ -395,7 +496,8 @@ huff_status huff_decode(huff_ctx* c, const uint32_t* d_words, uint64_t nwords, c
     a.use_sub = sub_size ? 1 : 0;
     a.nitems = (n + item - 1) / item;
     a.err = c->status;
-    return hip_status(launch_decode(a, c->params.dec_block, as_stream(stream)));
+    KernelTimer kt(c, HUFF_K_DECODE, as_stream(stream));
+    return hip_status(launch_decode(a, c->params.dec_block, ((uintptr_t)d_out & 15u) == 0, as_stream(stream)));
 }
 
 huff_status huff_copy(huff_ctx* c, const void* d_src, void* d_dst, uint64_t bytes, void* stream) {
@@ -433,12 +535,15 @@ huff_status batch_tables(const huff_file* files, uint32_t nfiles, uint32_t chunk
     t.enc.assign(nfiles, FileDesc{});
     t.dec.assign(nfiles, FileDesc{});
     t.ntiles = t.nitems = 0;
+    t.can_decode = true;
     const uint32_t item = sub_size ? sub_size : chunk_size;
     for (uint32_t i = 0; i < nfiles; ++i) {
         const huff_file& f = files[i];
         if (f.n >= kMaxN || !dcb_ok(f.cb) || !f.chunk_off || (sub_size && !f.sub_lo)) return HUFF_E_INVAL;
         if (f.n && ((!decode_only && !f.in) || !f.words || ((uintptr_t)f.words & 15u))) return HUFF_E_INVAL;
         if (f.n && decode_only && !f.out) return HUFF_E_INVAL;
+        if (f.n && f.out && ((uintptr_t)f.out & 15u)) return HUFF_E_INVAL;
+        if (f.n && !f.out) t.can_decode = false;
         FileDesc d;
         memset(&d, 0, sizeof(d));
         d.in = f.in;
@@ -487,7 +592,7 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
         a.use_sub = b->sub_size ? 1 : 0;
         a.nitems = b->nitems;
         a.err = c->status;
-        return hip_status(launch_decode(a, kDecBatchBlock, s));
+        return hip_status(launch_decode(a, kDecBatchBlock, true, s));
     }
     if (b->ntiles > 0) {
         // per-tile histograms of every file
@@ -516,15 +621,25 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
         if (st != HUFF_OK) return st;
     }
     if (b->ntiles == 0) return HUFF_OK;
+    // tile bits into d_tile_local, scanned there in place
+    TileBitsArgs ta;
+    memset(&ta, 0, sizeof(ta));
+    ta.tile_hist = b->d_tile_hist;
+    ta.files = b->d_enc;
+    ta.tile_file = b->d_tile_file;
+    ta.ntiles = b->ntiles;
+    ta.tile_bits = b->d_tile_local;
+    huff_status st = hip_status(launch_tile_bits_hist(ta, s));
+    if (st != HUFF_OK) return st;
     ScanArgs sa;
     memset(&sa, 0, sizeof(sa));
-    sa.tile_hist = b->d_tile_hist;
+    sa.tile_bits = b->d_tile_local;
     sa.files = b->d_enc;
     sa.tile_file = b->d_tile_file;
     sa.ntiles = b->ntiles;
     sa.tile_local = b->d_tile_local;
     sa.blk_tail = b->d_blk_tail;
-    huff_status st = hip_status(launch_tile_scan(sa, s));
+    st = hip_status(launch_tile_scan(sa, s));
     if (st != HUFF_OK) return st;
     st = hip_status(launch_blk_scan(b->d_blk_tail, b->d_blk_carry, (b->ntiles + kScanTilesPerBlock - 1) / kScanTilesPerBlock, s));
     if (st != HUFF_OK) return st;
@@ -585,6 +700,7 @@ huff_status huff_batch_create(huff_ctx* c, const huff_file* files, uint32_t nfil
     b->sub_size = sub_size;
     b->ntiles = t.ntiles;
     b->nitems = t.nitems;
+    b->can_decode = t.can_decode;
     const uint64_t ntiles = t.ntiles;
     const uint64_t nblk = ntiles / kScanTilesPerBlock + 1;
     const size_t fbytes = std::max<size_t>(1, nfiles) * sizeof(FileDesc);
@@ -613,6 +729,7 @@ void huff_batch_destroy(huff_batch* b) {
 
 huff_status huff_batch_run(huff_batch* b, int op, int use_graph, void* stream) {
     if (!b || op < HUFF_OP_COMPRESS || op > HUFF_OP_DECODE) return HUFF_E_INVAL;
+    if (op == HUFF_OP_DECODE && !b->can_decode) return HUFF_E_INVAL;  // a non-empty file has no output buffer
     DeviceGuard g(b->device);
     hipStream_t s = as_stream(stream);
     if (!use_graph) return batch_launch(b, op, s);

@@ -66,11 +66,19 @@ constexpr unsigned long long kTailStarts = 1ull << 63;  // the block's last segm
 constexpr unsigned long long kTailHead = 1ull << 62;    // a file starts at the block's first tile
 constexpr unsigned long long kTailBits = kTailHead - 1;
 
-struct ScanArgs {
-    const uint16_t* tile_hist;  // per-tile histograms, or ...
-    const uint32_t* tile_bits;  // ... per-tile bit counts
+// Per-tile code bits from the per-tile histograms (k_tile_bits_hist).
+struct TileBitsArgs {
+    const uint16_t* tile_hist;  // [ntiles][256] u16 counts
     const huff_dcb* cb;         // single file: its codebook
     const FileDesc* files;      // batch: file table (codebook per file) ...
+    const uint32_t* tile_file;  // ... and file index of every tile
+    uint64_t ntiles;
+    uint32_t* tile_bits;        // out: code bits of each tile
+};
+
+struct ScanArgs {
+    const uint32_t* tile_bits;  // code bits of each tile
+    const FileDesc* files;      // batch: file table ...
     const uint32_t* tile_file;  // ... and file index of every tile
     uint64_t ntiles;
     uint32_t* tile_local;
@@ -119,11 +127,13 @@ hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s);
 hipError_t launch_codebook(const CbArgs& a, uint32_t nblocks, hipStream_t s);
 hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, uint32_t* tile_bits, hipStream_t s);
 hipError_t launch_tile_scan(const ScanArgs& a, hipStream_t s);
+hipError_t launch_tile_bits_hist(const TileBitsArgs& a, hipStream_t s);
 hipError_t launch_blk_scan(const unsigned long long* blk_tail, unsigned long long* blk_carry, uint64_t nblk,
                            hipStream_t s);
 hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo, hipStream_t s);
-hipError_t launch_decode(const DecArgs& a, uint32_t block, hipStream_t s);
+// out_aligned: every output is 16-byte aligned (the staged decoder requires it)
+hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);

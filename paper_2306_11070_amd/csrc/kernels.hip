@@ -513,31 +513,43 @@ __global__ __launch_bounds__(kEncThreads) void k_tile_bits(const uint8_t* in, ui
     }
 }
 
+// Code bits of every tile from its u16 histogram: sum over byte values of
+// count x code length.  One wave per tile; lane l takes values 4l..4l+3, so
+// the tile's 512-byte histogram is one coalesced 8-byte load per lane.  A
+// batch takes each tile's lengths from its file's codebook.
+template <bool kBatch>
+__global__ __launch_bounds__(256) void k_tile_bits_hist(TileBitsArgs a) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t t = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (t >= a.ntiles) return;  // the whole wave
+    const huff_dcb* cb = a.cb;
+    if constexpr (kBatch) cb = a.files[a.tile_file[t]].cb;
+    const uint2 h = reinterpret_cast<const uint2*>(a.tile_hist + t * 256)[lane];
+    const uint32_t l4 = reinterpret_cast<const uint32_t*>(cb->len)[lane];
+    uint32_t bits = (h.x & 0xffffu) * (l4 & 0xffu) + (h.x >> 16) * ((l4 >> 8) & 0xffu) +
+                    (h.y & 0xffffu) * ((l4 >> 16) & 0xffu) + (h.y >> 16) * (l4 >> 24);
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) bits += __shfl_xor(bits, d, 64);
+    if (lane == 0) a.tile_bits[t] = bits;
+}
+
+hipError_t launch_tile_bits_hist(const TileBitsArgs& a, hipStream_t s) {
+    if (a.ntiles == 0) return hipSuccess;
+    const uint64_t blocks = (a.ntiles + 3) / 4;
+    if (a.files) hipLaunchKernelGGL(k_tile_bits_hist<true>, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL(k_tile_bits_hist<false>, dim3((uint32_t)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// One stream: exclusive scan of the tile bits inside blocks of kScanTiles
+// tiles, one thread per tile, and each block's total.  tile_local may be the
+// tile_bits buffer itself (each thread reads its tile's count before it
+// writes that tile's offset).
 __global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
-    __shared__ uint32_t s_len[256];
     __shared__ uint32_t s_wsum[kScanTiles / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < 256) s_len[tid] = a.cb->len[tid];
-    __syncthreads();
     const uint64_t t = (uint64_t)blockIdx.x * kScanTiles + tid;
-    uint32_t bits = 0;
-    if (t < a.ntiles) {
-        if (a.tile_hist) {
-            const uint4* h = reinterpret_cast<const uint4*>(a.tile_hist + t * 256);
-#pragma unroll 4
-            for (int i = 0; i < 32; ++i) {
-                const uint4 c = h[i];
-                const uint32_t w[4] = {c.x, c.y, c.z, c.w};
-#pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    bits += (w[k] & 0xffffu) * s_len[8 * i + 2 * k];
-                    bits += (w[k] >> 16) * s_len[8 * i + 2 * k + 1];
-                }
-            }
-        } else {
-            bits = a.tile_bits[t];
-        }
-    }
+    const uint32_t bits = t < a.ntiles ? a.tile_bits[t] : 0u;
     const uint32_t incl = wave_incl_scan(bits);
     if (lane == 63) s_wsum[wave] = incl;
     __syncthreads();
@@ -552,51 +564,21 @@ __global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
 }
 
 // Batch: the same scan restarted at every file.  One workgroup per block of
-// kScanTiles tiles, one thread per tile.
+// kScanTiles tiles, one thread per tile; tile_local may be the tile_bits
+// buffer itself.
 __global__ __launch_bounds__(kScanTiles) void k_tile_scan_seg(ScanArgs a) {
-    __shared__ uint32_t s_len[256];
     __shared__ uint32_t s_wsum[kScanTiles / 64];
     __shared__ uint32_t s_excl[kScanTiles];
     __shared__ uint32_t s_head;
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    if (tid < 256 && !a.files) s_len[tid] = a.cb->len[tid];
-    __syncthreads();
     const uint64_t b0 = (uint64_t)blockIdx.x * kScanTiles;
     const uint64_t t = b0 + tid;
     const uint64_t last = min<uint64_t>(a.ntiles, b0 + kScanTiles) - 1;
     uint32_t bits = 0;
     uint64_t first = 0;  // first tile of the tile's file
     if (t < a.ntiles) {
-        const huff_dcb* cb = a.cb;
-        if (a.files) {
-            const FileDesc& d = a.files[a.tile_file[t]];
-            first = d.first;
-            cb = d.cb;
-        }
-        if (a.tile_hist) {
-            // bits = sum over byte values of count x code length
-            const uint4* h = reinterpret_cast<const uint4*>(a.tile_hist + t * 256);
-            const uint4* ln = reinterpret_cast<const uint4*>(cb->len);
-            for (int i = 0; i < 16; ++i) {
-                const uint4 c0 = h[2 * i], c1 = h[2 * i + 1];
-                const uint32_t w[8] = {c0.x, c0.y, c0.z, c0.w, c1.x, c1.y, c1.z, c1.w};
-                uint32_t lw[4] = {0, 0, 0, 0};
-                if (a.files) {
-                    const uint4 l4 = ln[i];  // lengths of values 16i .. 16i+15
-                    lw[0] = l4.x, lw[1] = l4.y, lw[2] = l4.z, lw[3] = l4.w;
-                }
-#pragma unroll
-                for (int k = 0; k < 8; ++k) {
-                    const int v = 16 * i + 2 * k;
-                    const uint32_t sh = 16 * (k & 1);
-                    const uint32_t l0 = a.files ? (lw[k >> 1] >> sh) & 0xffu : s_len[v];
-                    const uint32_t l1 = a.files ? (lw[k >> 1] >> (sh + 8)) & 0xffu : s_len[v + 1];
-                    bits += (w[k] & 0xffffu) * l0 + (w[k] >> 16) * l1;
-                }
-            }
-        } else {
-            bits = a.tile_bits[t];
-        }
+        first = a.files[a.tile_file[t]].first;
+        bits = a.tile_bits[t];
     }
     const uint32_t incl = wave_incl_scan(bits);
     if (lane == 63) s_wsum[wave] = incl;
@@ -1178,6 +1160,51 @@ __device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lut
     return e & 0xffu;
 }
 
+constexpr int kDecLine = 64;  // bytes a decode lane stores together
+
+// 16 symbols, packed into 16 bytes in stream order.
+template <class Rd, typename U>
+__device__ __forceinline__ uint4 dec16(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad, U& used) {
+    uint32_t o[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < 16; ++i) o[i >> 2] |= dec1(r, t, lutBits, maxLen, bad, used) << (8 * (i & 3));
+    return make_uint4(o[0], o[1], o[2], o[3]);
+}
+
+// Decodes nsym symbols into out (16-byte aligned).  Each lane writes its own
+// region, so the lanes of one store instruction hit different cache lines; a
+// line written 16 bytes at a time, far apart in time, leaves L2 in pieces.
+// A lane therefore holds its last kLine / 16 groups of 16 decoded bytes in a
+// register queue and stores them together once kLine bytes are complete, so
+// that every kLine-byte piece of a line is written whole.
+template <int kLine, class Rd, typename U>
+__device__ __forceinline__ void dec_run(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+                                        U& used, uint8_t* out, uint32_t nsym) {
+    constexpr uint32_t kG = kLine / 16;  // groups held before they are stored
+    uint4* o4 = reinterpret_cast<uint4*>(out);
+    const uint32_t groups = nsym >> 4;
+    uint4 q[kG];  // q[kG - 1] is the newest group
+#pragma unroll
+    for (uint32_t k = 0; k < kG; ++k) q[k] = make_uint4(0, 0, 0, 0);
+#pragma unroll 1
+    for (uint32_t gi = 0; gi < groups; ++gi) {
+        const uint4 v = dec16(r, t, lutBits, maxLen, bad, used);
+#pragma unroll
+        for (uint32_t k = 0; k + 1 < kG; ++k) q[k] = q[k + 1];
+        q[kG - 1] = v;
+        if (((gi + 1) & (kG - 1)) == 0) {
+#pragma unroll
+            for (uint32_t k = 0; k < kG; ++k) o4[gi + 1 - kG + k] = q[k];
+        }
+    }
+    // groups left in the queue: the last (groups mod kG)
+    const uint32_t rest = groups & (kG - 1);
+#pragma unroll
+    for (uint32_t k = 0; k < kG; ++k)
+        if (k + rest >= kG) o4[groups - kG + k] = q[k];
+    for (uint32_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)dec1(r, t, lutBits, maxLen, bad, used);
+}
+
 // Codes longer than 32 bits: canonical search on a 64-bit peek from memory.
 __device__ void decode_generic(const FileDesc& f, const DecTables& t, uint32_t maxLen, uint64_t start, uint64_t nsym,
                                uint8_t* out, bool& bad, uint64_t& used) {
@@ -1248,20 +1275,11 @@ __global__ __launch_bounds__(256) void k_decode(DecArgs a) {
     if (!bad && maxLen <= 32) {
         BitReader br;
         br.init(f.words, f.nwords, start);
-        const uint64_t groups = nsym >> 4;
-        const bool vec_ok = (((uintptr_t)out) & 15u) == 0;
-        for (uint64_t gi = 0; gi < groups; ++gi) {
-            uint32_t o[4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int i = 0; i < 16; ++i) o[i >> 2] |= dec1(br, t, lutBits, maxLen, bad, used) << (8 * (i & 3));
-            if (vec_ok) {
-                reinterpret_cast<uint4*>(out)[gi] = make_uint4(o[0], o[1], o[2], o[3]);
-            } else {
-#pragma unroll
-                for (int i = 0; i < 16; ++i) out[gi * 16 + i] = (uint8_t)(o[i >> 2] >> (8 * (i & 3)));
-            }
+        if ((((uintptr_t)out) & 15u) == 0) {
+            dec_run<kDecLine>(br, t, lutBits, maxLen, bad, used, out, (uint32_t)nsym);
+        } else {
+            for (uint64_t i = 0; i < nsym; ++i) out[i] = (uint8_t)dec1(br, t, lutBits, maxLen, bad, used);
         }
-        for (uint64_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)dec1(br, t, lutBits, maxLen, bad, used);
     } else if (!bad) {
         decode_generic(f, t, maxLen, start, nsym, out, bad, used);
     }
@@ -1342,38 +1360,22 @@ __global__ __launch_bounds__(256) void k_decode_staged(DecArgs a) {
         return;
     }
     uint32_t used = 0;
-    auto run = [&](auto& rd) {
-        const uint32_t groups = nsym >> 4;
-#pragma unroll 1
-        for (uint32_t gi = 0; gi < groups; ++gi) {
-            uint32_t o0 = 0, o1 = 0, o2 = 0, o3 = 0;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) o0 |= dec1(rd, t, lutBits, maxLen, bad, used) << (8 * i);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) o1 |= dec1(rd, t, lutBits, maxLen, bad, used) << (8 * i);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) o2 |= dec1(rd, t, lutBits, maxLen, bad, used) << (8 * i);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) o3 |= dec1(rd, t, lutBits, maxLen, bad, used) << (8 * i);
-            reinterpret_cast<uint4*>(out)[gi] = make_uint4(o0, o1, o2, o3);
-        }
-        for (uint32_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)dec1(rd, t, lutBits, maxLen, bad, used);
-    };
+    constexpr int kLine = S < kDecLine ? S : kDecLine;
     if (staged) {
         LdsReader rd;
         rd.init(s_in[wave], kInWords, (uint32_t)(start - (base << 5)));
-        run(rd);
+        dec_run<kLine>(rd, t, lutBits, maxLen, bad, used, out, nsym);
     } else {
         BitReader rd;
         rd.init(f.words, f.nwords, start);
-        run(rd);
+        dec_run<kLine>(rd, t, lutBits, maxLen, bad, used, out, nsym);
     }
     if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
 }
 
-hipError_t launch_decode(const DecArgs& a, uint32_t block, hipStream_t s) {
+hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hipStream_t s) {
     const uint32_t sub = 1u << a.item_log2;
-    if (a.use_sub && sub >= 32 && sub <= 256) {
+    if (a.use_sub && sub >= 32 && sub <= 256 && out_aligned) {
         const uint64_t blocks = (a.nitems + 255) / 256;
 #define HUFF_STAGED(SZ)                                                                                      \
     if (sub == SZ) {                                                                                         \

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -22,6 +23,10 @@ struct huff_ctx {
     unsigned long long* blk_carry = nullptr;  // [tile_cap / 1024 + 1]
     uint64_t tile_cap = 0;
     int32_t* status = nullptr;
+    // kernel timing (huff_ctx_set_timing): event pairs per kernel id
+    bool timing = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[HUFF_K_COUNT];
+    std::vector<hipEvent_t> spare_events;
 };
 
 // A batch plan: device file tables and per-tile workspaces for a set of
@@ -32,6 +37,7 @@ struct huff_batch {
     int device = 0;              // ctx's device (destroy may run after the context is gone)
     uint32_t nfiles = 0, chunk_size = 0, sub_size = 0;
     uint64_t ntiles = 0, nitems = 0;
+    bool can_decode = false;     // every non-empty file has an output buffer
     huff::FileDesc* d_enc = nullptr;   // [nfiles], first = first tile
     huff::FileDesc* d_dec = nullptr;   // [nfiles], first = first decode lane (256-aligned)
     uint32_t* d_tile_file = nullptr;
@@ -75,6 +81,7 @@ struct BatchTables {
     std::vector<FileDesc> dec;       // first = first decode lane (kDecBatchBlock-aligned)
     std::vector<uint32_t> tile_file; // tile -> file
     uint64_t ntiles = 0, nitems = 0;
+    bool can_decode = true;          // every non-empty file has an output buffer
 };
 
 // Validates `files` and fills `t`.  HUFF_E_INVAL on a bad file or sizes.

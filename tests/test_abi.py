@@ -119,3 +119,12 @@ def test_host_codebook_matches_oracle(case):
     assert np.array_equal(code, oracle.canonical_codes(oln))
     assert cb.nsym == int(np.count_nonzero(oln)) and cb.max_len == int(oln.max())
     assert P.encoded_bits(h, cb) == oracle.total_bits(h, oln)
+
+
+def test_timing_calls_reject_null_context_without_device():
+    lib = P.load()
+    ms, k = ctypes.c_double(), ctypes.c_uint64()
+    assert lib.huff_ctx_set_timing(None, 1) == _abi.HUFF_E_INVAL
+    assert lib.huff_ctx_kernel_time(None, _abi.HUFF_K_ENCODE, ctypes.byref(ms), ctypes.byref(k), 1) == _abi.HUFF_E_INVAL
+    assert set(_abi.KERNEL_IDS.values()) == set(range(5))
+

@@ -203,3 +203,20 @@ def test_batch_many_files_log_uniform(P, codec):
         _check_file(f, a, chunk, sub)
         assert np.array_equal(f["out"].cpu().numpy(), a)
     b.close()
+
+
+def test_batch_decode_needs_outputs(P, codec):
+    """A plan whose non-empty file has no output buffer refuses to decode
+    (before any launch) and still compresses."""
+    _say("batch decode without outputs")
+    data = [_file_data(i, n) for i, n in enumerate([5_000, 0, 20_000])]
+    files = P.batch_buffers(codec, [dev(a) for a in data], 4096, 64, decode=False)
+    b = P.Batch(codec, files, 4096, 64)
+    with pytest.raises(P.HuffError):
+        b.decode()
+    b.compress()
+    torch.cuda.synchronize()
+    for f, a in zip(files, data):
+        _check_file(f, a, 4096, 64)
+    b.close()
+

@@ -255,6 +255,22 @@ def test_unaligned_input(codec, off, kind):
     assert np.array_equal(out.cpu().numpy(), a)
 
 
+@pytest.mark.parametrize("sub", [0, 32, 256])
+@pytest.mark.parametrize("off", [1, 8])
+def test_decode_unaligned_output(codec, sub, off):
+    """Output buffers at a byte skew: the decoder that stores whole 16-byte
+    groups is not used, the bytes are still exact."""
+    _say(f"unaligned output off={off} sub={sub}")
+    a = _data("markov", 77_777, seed=off)
+    c = codec.compress(dev(a), 1024, sub)
+    buf = torch.full((a.size + off,), 0xEE, dtype=torch.uint8, device="cuda")
+    st = codec.new_status()
+    codec.decompress(c, out=buf[off:], status=st)
+    _check_status(st)
+    got = buf.cpu().numpy()
+    assert np.array_equal(got[off:], a) and np.all(got[:off] == 0xEE)
+
+
 def test_many_launches_reuse_workspace(codec):
     """The encode workspace resets itself: many calls of varying size in a row."""
     _say("many launches")
