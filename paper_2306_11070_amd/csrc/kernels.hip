@@ -1119,37 +1119,49 @@ __device__ __noinline__ uint32_t decode_long(const DecTables& t, uint32_t top, u
 }
 
 // Reader over words staged in LDS (word 0 = the first staged stream word).
+// The refill has no branch: `pre` always holds the word at index `nxt` and is
+// re-read after every symbol, so the word a refill takes was loaded at least
+// one symbol earlier and the refill never waits for LDS.  Indexes are clamped
+// to the wave's buffer; words past a sub-block's end only ever fill the
+// window's tail, which the table lookups of its last codes do not depend on.
 struct LdsReader {
     const uint32_t* s;
-    uint32_t lim, nxt, pre;
+    uint32_t last, nxt, pre;  // last: index of the buffer's last word
     uint64_t win;
     uint32_t avail;
-    __device__ __forceinline__ uint32_t get(uint32_t i) const { return i < lim ? s[i] : 0u; }
-    __device__ __forceinline__ void init(const uint32_t* s_, uint32_t lim_, uint32_t bit) {
+    __device__ __forceinline__ uint32_t at(uint32_t i) const { return s[i < last ? i : last]; }
+    __device__ __forceinline__ void init(const uint32_t* s_, uint32_t lim, uint32_t bit) {
         s = s_;
-        lim = lim_;
+        last = lim - 1;
         const uint32_t wi = bit >> 5, sk = bit & 31;
-        win = (((uint64_t)get(wi) << 32) | get(wi + 1)) << sk;
+        win = (((uint64_t)at(wi) << 32) | at(wi + 1)) << sk;
         avail = 64 - sk;
         nxt = wi + 2;
-        pre = get(nxt);
+        pre = at(nxt);
     }
     __device__ __forceinline__ void refill() {
-        if (avail < 32) {
-            win |= (uint64_t)pre << (32 - avail);
-            avail += 32;
-            pre = get(++nxt);
-        }
+        const bool need = avail < 32;
+        const uint64_t add = (uint64_t)pre << ((32u - avail) & 63u);
+        win |= need ? add : 0ull;
+        avail += need ? 32u : 0u;
+        nxt += need ? 1u : 0u;
+        pre = at(nxt);
     }
 };
 
 // One symbol from a reader whose window holds >= 32 valid bits after refill.
-template <class Rd, typename U>
-__device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad, U& used) {
+// kFits: every code is at most lutBits long, so the table alone decodes; a
+// table entry of 0 (no code matches) is then kept in emin and reported by
+// the caller instead of being branched on per symbol.
+template <bool kFits, class Rd, typename U>
+__device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+                                         U& used, uint32_t& emin) {
     r.refill();
     const uint32_t top = (uint32_t)(r.win >> 32);
     uint32_t e = t.lut[top >> (32 - lutBits)];
-    if ((e >> 8) == 0) {
+    if constexpr (kFits) {
+        emin = min(emin, e);
+    } else if ((e >> 8) == 0) {
         e = decode_long(t, top, lutBits, maxLen);
         if (e == 0) { bad = true; e = 1u << 8; }
     }
@@ -1163,11 +1175,13 @@ __device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lut
 constexpr int kDecLine = 64;  // bytes a decode lane stores together
 
 // 16 symbols, packed into 16 bytes in stream order.
-template <class Rd, typename U>
-__device__ __forceinline__ uint4 dec16(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad, U& used) {
+template <bool kFits, class Rd, typename U>
+__device__ __forceinline__ uint4 dec16(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad, U& used,
+                                       uint32_t& emin) {
     uint32_t o[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < 16; ++i) o[i >> 2] |= dec1(r, t, lutBits, maxLen, bad, used) << (8 * (i & 3));
+    for (int i = 0; i < 16; ++i)
+        o[i >> 2] |= dec1<kFits>(r, t, lutBits, maxLen, bad, used, emin) << (8 * (i & 3));
     return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
@@ -1177,9 +1191,10 @@ __device__ __forceinline__ uint4 dec16(Rd& r, const DecTables& t, uint32_t lutBi
 // A lane therefore holds its last kLine / 16 groups of 16 decoded bytes in a
 // register queue and stores them together once kLine bytes are complete, so
 // that every kLine-byte piece of a line is written whole.
-template <int kLine, class Rd, typename U>
-__device__ __forceinline__ void dec_run(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
-                                        U& used, uint8_t* out, uint32_t nsym) {
+template <int kLine, bool kFits, class Rd, typename U>
+__device__ __forceinline__ void dec_run_k(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+                                          U& used, uint8_t* out, uint32_t nsym) {
+    uint32_t emin = 0xffffffffu;
     constexpr uint32_t kG = kLine / 16;  // groups held before they are stored
     uint4* o4 = reinterpret_cast<uint4*>(out);
     const uint32_t groups = nsym >> 4;
@@ -1188,7 +1203,7 @@ __device__ __forceinline__ void dec_run(Rd& r, const DecTables& t, uint32_t lutB
     for (uint32_t k = 0; k < kG; ++k) q[k] = make_uint4(0, 0, 0, 0);
 #pragma unroll 1
     for (uint32_t gi = 0; gi < groups; ++gi) {
-        const uint4 v = dec16(r, t, lutBits, maxLen, bad, used);
+        const uint4 v = dec16<kFits>(r, t, lutBits, maxLen, bad, used, emin);
 #pragma unroll
         for (uint32_t k = 0; k + 1 < kG; ++k) q[k] = q[k + 1];
         q[kG - 1] = v;
@@ -1202,7 +1217,16 @@ __device__ __forceinline__ void dec_run(Rd& r, const DecTables& t, uint32_t lutB
 #pragma unroll
     for (uint32_t k = 0; k < kG; ++k)
         if (k + rest >= kG) o4[groups - kG + k] = q[k];
-    for (uint32_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)dec1(r, t, lutBits, maxLen, bad, used);
+    for (uint32_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)dec1<kFits>(r, t, lutBits, maxLen, bad, used, emin);
+    if (kFits && emin < 256u) bad = true;
+}
+
+// Picks the table-only decoder when every code fits the table.
+template <int kLine, class Rd, typename U>
+__device__ __forceinline__ void dec_run(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+                                        U& used, uint8_t* out, uint32_t nsym) {
+    if (maxLen <= lutBits) dec_run_k<kLine, true>(r, t, lutBits, maxLen, bad, used, out, nsym);
+    else dec_run_k<kLine, false>(r, t, lutBits, maxLen, bad, used, out, nsym);
 }
 
 // Codes longer than 32 bits: canonical search on a 64-bit peek from memory.
@@ -1278,7 +1302,8 @@ __global__ __launch_bounds__(256) void k_decode(DecArgs a) {
         if ((((uintptr_t)out) & 15u) == 0) {
             dec_run<kDecLine>(br, t, lutBits, maxLen, bad, used, out, (uint32_t)nsym);
         } else {
-            for (uint64_t i = 0; i < nsym; ++i) out[i] = (uint8_t)dec1(br, t, lutBits, maxLen, bad, used);
+            uint32_t emin = 0;  // unused by the general decoder
+            for (uint64_t i = 0; i < nsym; ++i) out[i] = (uint8_t)dec1<false>(br, t, lutBits, maxLen, bad, used, emin);
         }
     } else if (!bad) {
         decode_generic(f, t, maxLen, start, nsym, out, bad, used);
