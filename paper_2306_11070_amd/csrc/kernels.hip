@@ -260,14 +260,13 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
     __shared__ uint8_t s_sorted[256];
     __shared__ uint32_t s_cnt[64], s_fidx[64];
     __shared__ unsigned long long s_first[64];
-    __shared__ unsigned long long s_tot, s_n;
-    __shared__ uint32_t s_max;
+    __shared__ uint32_t s_wcnt[64][kCbThreads / 64];  // bytes of each length, per wave
+    __shared__ unsigned long long s_red_t[kCbThreads / 64], s_red_n[kCbThreads / 64];
+    __shared__ uint32_t s_red_m[kCbThreads / 64];
     const uint32_t v = threadIdx.x;
     uint64_t h = 0;
     uint32_t myLen = 0;
     int32_t status = HUFF_OK;
-    if (v == 0) { s_tot = 0; s_n = 0; s_max = 0; }
-    if (v < 64) s_cnt[v] = 0;
     huff_dcb* d = a.out;
     int32_t* err = a.err;
     if (!a.from_lengths) {
@@ -328,27 +327,24 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
                 const uint32_t cI = (uint32_t)__syncthreads_count(intIn);
                 const uint32_t pairs = (cL + cI) >> 1;
                 // merged position of each node taking part
-                uint32_t posL = ~0u;
-                if (leafIn) {
-                    const uint64_t key2 = s_w[li + v];
-                    uint32_t lo = 0, hi = cI;  // internal nodes strictly lighter
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (s_w[K + qi + mid] < key2) lo = mid + 1; else hi = mid;
+                // both binary searches in one loop, so that their LDS reads overlap:
+                // for the leaf, internal nodes strictly lighter; for the internal
+                // node, leaves at most as heavy
+                const uint64_t keyL = leafIn ? s_w[li + v] : 0ull, keyI = intIn ? s_w[K + qi + v] : 0ull;
+                uint32_t loL = 0, hiL = leafIn ? cI : 0u, loI = 0, hiI = intIn ? cL : 0u;
+                while (loL < hiL || loI < hiI) {
+                    const uint32_t mL = (loL + hiL) >> 1, mI = (loI + hiI) >> 1;
+                    const uint64_t wL = s_w[K + qi + mL], wI = s_w[li + mI];
+                    if (loL < hiL) {
+                        if (wL < keyL) loL = mL + 1; else hiL = mL;
                     }
-                    posL = v + lo;
-                    if (posL < 2 * pairs) s_m[posL] = (uint16_t)(li + v);
-                }
-                if (intIn) {
-                    const uint64_t key2 = s_w[K + qi + v];
-                    uint32_t lo = 0, hi = cL;  // leaves at most as heavy
-                    while (lo < hi) {
-                        const uint32_t mid = (lo + hi) >> 1;
-                        if (s_w[li + mid] <= key2) lo = mid + 1; else hi = mid;
+                    if (loI < hiI) {
+                        if (wI <= keyI) loI = mI + 1; else hiI = mI;
                     }
-                    const uint32_t pos = v + lo;
-                    if (pos < 2 * pairs) s_m[pos] = (uint16_t)(K + qi + v);
                 }
+                const uint32_t posL = leafIn ? v + loL : ~0u;
+                if (posL < 2 * pairs) s_m[posL] = (uint16_t)(li + v);
+                if (intIn && v + loI < 2 * pairs) s_m[v + loI] = (uint16_t)(K + qi + v);
                 const uint32_t nl = (uint32_t)__syncthreads_count(posL < 2 * pairs);
                 if (v < pairs) {
                     const uint32_t x = s_m[2 * v], y = s_m[2 * v + 1];
@@ -394,20 +390,53 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
             __syncthreads();
             myLen = h ? s_len[v] : 0u;
         }
-        atomicAdd(&s_tot, (unsigned long long)(h * myLen));
-        atomicAdd(&s_n, (unsigned long long)h);
     } else {
         myLen = a.len[v];
     }
+    // totals by wave reductions (no same-address atomics): n = sum h,
+    // T = sum h * len, longest code
+    const uint32_t lane = v & 63, wave = v >> 6;
+    {
+        const uint64_t wt = wave_sum_u64(h * myLen), wn = wave_sum_u64(h);
+        uint32_t wm = myLen;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) wm = max(wm, (uint32_t)__shfl_xor(wm, o, 64));
+        if (lane == 0) {
+            s_red_t[wave] = wt;
+            s_red_n[wave] = wn;
+            s_red_m[wave] = wm;
+        }
+    }
+    s_sorted[v] = 0;
     __syncthreads();
-    s_len[v] = (uint8_t)myLen;
-    if (myLen) {
-        atomicMax(&s_max, myLen);
-        if (myLen < 64) atomicAdd(&s_cnt[myLen], 1u);
+    uint64_t tot = 0, nn = 0;
+    uint32_t maxLen = 0;
+#pragma unroll
+    for (int w = 0; w < kCbThreads / 64; ++w) {
+        tot += s_red_t[w];
+        nn += s_red_n[w];
+        maxLen = max(maxLen, s_red_m[w]);
+    }
+    if (maxLen > HUFF_MAX_CODE_LEN) status = HUFF_E_CODELEN;
+    // counting sort of the present bytes by (length, value): per wave, one
+    // ballot per length gives that length's count and each byte's rank among
+    // the bytes of its length in lower lanes (lower byte values)
+    const uint32_t lmax = maxLen < 64 ? maxLen : 63;
+    uint32_t rank = 0;
+    const uint64_t below = (1ull << lane) - 1;
+    for (uint32_t l = 1; l <= lmax; ++l) {
+        const uint64_t m = __ballot(myLen == l);
+        if (myLen == l) rank = (uint32_t)__popcll(m & below);
+        if (lane == 0) s_wcnt[l][wave] = (uint32_t)__popcll(m);
     }
     __syncthreads();
-    const uint32_t maxLen = s_max;
-    if (maxLen > HUFF_MAX_CODE_LEN) status = HUFF_E_CODELEN;
+    if (v < 64) {
+        uint32_t c = 0;
+        if (v >= 1 && v <= lmax)
+            for (int w = 0; w < kCbThreads / 64; ++w) c += s_wcnt[v][w];
+        s_cnt[v] = c;
+    }
+    __syncthreads();
     if (v < 64) {
         // first canonical code of length v: sum over j < v of count[j] * 2^(v-j)
         uint32_t fidx = 0;
@@ -419,22 +448,16 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
         s_fidx[v] = fidx;
         s_first[v] = fc;
     }
-    // present bytes in (length, value) order: position -> canonical code
-    const uint32_t K2 = (uint32_t)__syncthreads_count(myLen != 0 && myLen < 64);
-    const uint64_t key = sort256(myLen && myLen < 64 ? ((uint64_t)myLen << 8) | v : 0ull, s_tmp);
-    s_sorted[v] = 0;
     __syncthreads();
-    uint64_t* codes = reinterpret_cast<uint64_t*>(s_w);  // reuse: code per byte value
-    codes[v] = 0;
-    __syncthreads();
-    if (v >= 256 - K2) {
-        const uint32_t i = v - (256 - K2);
-        const uint32_t sym = (uint32_t)(key & 0xffu), l = (uint32_t)(key >> 8);
-        s_sorted[i] = (uint8_t)sym;
-        codes[sym] = s_first[l] + (i - s_fidx[l]);
+    // the byte's place in (length, value) order and its canonical code
+    uint64_t code = 0;
+    if (myLen && myLen < 64) {
+        uint32_t r = rank;
+        for (uint32_t w = 0; w < wave; ++w) r += s_wcnt[myLen][w];
+        code = s_first[myLen] + r;
+        s_sorted[s_fidx[myLen] + r] = (uint8_t)v;
     }
-    __syncthreads();
-    const uint64_t code = codes[v];
+    const uint32_t K2 = (uint32_t)__syncthreads_count(myLen != 0 && myLen < 64);
     const uint32_t lutBits = maxLen < HUFF_LUT_BITS ? maxLen : HUFF_LUT_BITS;
     d->len[v] = (uint8_t)myLen;
     d->code[v] = code;
@@ -463,8 +486,8 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
         d->max_len = maxLen;
         d->lut_bits = lutBits;
         d->status = status;
-        d->total_bits = a.from_lengths ? 0 : s_tot;
-        d->n = a.from_lengths ? 0 : s_n;
+        d->total_bits = a.from_lengths ? 0 : tot;
+        d->n = a.from_lengths ? 0 : nn;
         if (status != HUFF_OK) atomicMin(err, status);
     }
 }
