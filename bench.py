@@ -25,7 +25,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak, GB/s
 WORKLOADS = {
     # name: (description, chunk size, decode sub-block)
     "markov_45MiB": ("45 MiB order-2 Markov text over 96 printable bytes (Zipf(1.0) rows, newline after N(70,15)), "
-                     "global codebook, 256 KiB chunks", 256 << 10, 256),
+                     "global codebook, 256 KiB chunks, decode index every 128 bytes", 256 << 10, 128),
     "zipf96_1MiB": ("1 MiB i.i.d. Zipf(1.1) over 96 printable bytes, 64 KiB chunks", 64 << 10, 256),
     "markov_2GiB": ("2 GiB order-2 Markov text, 1 MiB chunks", 1 << 20, 256),
     "zipf256_2GiB": ("2 GiB i.i.d. Zipf(0.8) over 256 byte values, 1 MiB chunks", 1 << 20, 256),
@@ -366,6 +366,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {desc}", "n_bytes": n, "chunk_size": chunk, "sub_size": sub,
                    "bits_per_byte": round(T / n, 4), "max_code_len": int(d.max_len),
+                   "index_bytes": index_bytes, "stream_over_input": round((T / 8 + index_bytes) / n, 4),
                    "step": "huff_compress (histogram + device codebook + encode) + huff_decode"},
         "phases": {p: {"ms": round(phase_ms[p], 4), "alg_GBps": round(alg[p] / (phase_ms[p] * 1e-3) / 1e9, 1)}
                    for p in phase_ms},

@@ -288,9 +288,11 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
             sa.tile_bits = c->tile_bits;
             sa.ntiles = ntiles;
             sa.tile_local = c->tile_local;
-            sa.blk_total = c->blk_tail;  // one stream: the block-tail buffer holds block totals
+            sa.blk_tail = c->blk_tail;
             st = hip_status(launch_tile_scan(sa, s));
         }
+        if (st == HUFF_OK)
+            st = hip_status(launch_blk_scan(c->blk_tail, c->blk_carry, (ntiles + kScanTilesPerBlock - 1) / kScanTilesPerBlock, s));
     }
     if (st != HUFF_OK) return st;
     EncArgs a;
@@ -308,9 +310,10 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
     a.nfiles = 1;
     a.chunk_log2 = log2u(chunk_size);
     a.sub_log2 = sub_size ? log2u(sub_size) : kNoSub;
+    a.aligned = ((uintptr_t)d_in & 15u) == 0;
     a.ntiles = ntiles;
     a.tile_local = c->tile_local;
-    a.blk_total = c->blk_tail;
+    a.blk_carry = c->blk_carry;
     a.err = c->status;
     const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)c->num_cus * c->params.enc_blocks_per_cu);
     KernelTimer kt(c, HUFF_K_ENCODE, s);
@@ -535,6 +538,7 @@ huff_status batch_tables(const huff_file* files, uint32_t nfiles, uint32_t chunk
     t.enc.assign(nfiles, FileDesc{});
     t.dec.assign(nfiles, FileDesc{});
     t.ntiles = t.nitems = 0;
+    t.aligned = true;
     t.can_decode = true;
     const uint32_t item = sub_size ? sub_size : chunk_size;
     for (uint32_t i = 0; i < nfiles; ++i) {
@@ -544,6 +548,7 @@ huff_status batch_tables(const huff_file* files, uint32_t nfiles, uint32_t chunk
         if (f.n && decode_only && !f.out) return HUFF_E_INVAL;
         if (f.n && f.out && ((uintptr_t)f.out & 15u)) return HUFF_E_INVAL;
         if (f.n && !f.out) t.can_decode = false;
+        if (f.n && ((uintptr_t)f.in & 15u)) t.aligned = false;
         FileDesc d;
         memset(&d, 0, sizeof(d));
         d.in = f.in;
@@ -647,6 +652,7 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
     memset(&e, 0, sizeof(e));
     e.files = b->d_enc;
     e.nfiles = b->nfiles;
+    e.aligned = b->aligned ? 1u : 0u;
     e.chunk_log2 = log2u(b->chunk_size);
     e.sub_log2 = b->sub_size ? log2u(b->sub_size) : kNoSub;
     e.ntiles = b->ntiles;
@@ -701,6 +707,7 @@ huff_status huff_batch_create(huff_ctx* c, const huff_file* files, uint32_t nfil
     b->ntiles = t.ntiles;
     b->nitems = t.nitems;
     b->can_decode = t.can_decode;
+    b->aligned = t.aligned;
     const uint64_t ntiles = t.ntiles;
     const uint64_t nblk = ntiles / kScanTilesPerBlock + 1;
     const size_t fbytes = std::max<size_t>(1, nfiles) * sizeof(FileDesc);

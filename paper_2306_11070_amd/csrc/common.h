@@ -50,18 +50,19 @@ struct EncArgs {
     uint32_t nfiles;
     uint32_t chunk_log2;
     uint32_t sub_log2;      // kNoSub if no sub index
+    uint32_t aligned;       // every input is 16-byte aligned
     uint64_t ntiles;        // total over all files
     const uint32_t* tile_file;             // batch: file index of every tile
     const uint32_t* tile_local;            // tile's first bit inside its scan block (and, batch, its file)
-    const unsigned long long* blk_total;   // one stream: code bits of each scan block
-    const unsigned long long* blk_carry;   // batch: bits of the file open at a block's start, before the block
+    const unsigned long long* blk_carry;   // bits of the file open at a block's start, before the block
     int32_t* err;           // fallback status word
 };
 
-// Batch tile offsets are a scan segmented by file, in two levels:
-// k_tile_scan_seg scans the tiles of each 1024-tile block, k_blk_scan carries
-// the open file's running total from block to block.  blk_tail packs, per
-// block, the bits of its last segment (low 62 bits) with two flags.
+// Tile offsets are a scan in two levels, segmented by file in a batch:
+// k_tile_scan / k_tile_scan_seg scan the tiles of each 1024-tile block,
+// k_blk_scan carries the open file's running total from block to block.
+// blk_tail packs, per block, the bits of its last segment (low 62 bits) with
+// two flags.
 constexpr unsigned long long kTailStarts = 1ull << 63;  // the block's last segment starts inside the block
 constexpr unsigned long long kTailHead = 1ull << 62;    // a file starts at the block's first tile
 constexpr unsigned long long kTailBits = kTailHead - 1;
@@ -82,8 +83,7 @@ struct ScanArgs {
     const uint32_t* tile_file;  // ... and file index of every tile
     uint64_t ntiles;
     uint32_t* tile_local;
-    unsigned long long* blk_total;  // one stream: bits per scan block
-    unsigned long long* blk_tail;   // batch: last segment of each block, with flags
+    unsigned long long* blk_tail;   // last segment of each block, with flags
 };
 
 struct DecArgs {

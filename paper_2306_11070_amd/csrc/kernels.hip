@@ -565,7 +565,7 @@ hipError_t launch_tile_bits_hist(const TileBitsArgs& a, hipStream_t s) {
 }
 
 // One stream: exclusive scan of the tile bits inside blocks of kScanTiles
-// tiles, one thread per tile, and each block's total.  tile_local may be the
+// tiles, one thread per tile, and each block's total (as a block tail).  tile_local may be the
 // tile_bits buffer itself (each thread reads its tile's count before it
 // writes that tile's offset).
 __global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
@@ -583,7 +583,9 @@ __global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
         before += w < (int)wave ? ws : 0u;
     }
     if (t < a.ntiles) a.tile_local[t] = before + incl - bits;
-    if (tid == 0) a.blk_total[blockIdx.x] = total;
+    // the block's total as the tail of one segment (block 0 starts the stream),
+    // so that k_blk_scan turns the tails into block carries
+    if (tid == 0) a.blk_tail[blockIdx.x] = total | (blockIdx.x == 0 ? (kTailStarts | kTailHead) : 0ull);
 }
 
 // Batch: the same scan restarted at every file.  One workgroup per block of
@@ -649,7 +651,9 @@ __global__ __launch_bounds__(1024) void k_blk_scan(const unsigned long long* tai
         s_v[0][tid] = v;
         s_r[0][tid] = r;
         __syncthreads();
-        for (uint32_t d = 1; d < 1024; d <<= 1) {
+        // only as many steps as this pass has blocks (every later block has r = 1)
+        const uint32_t span = (uint32_t)min<uint64_t>(1024, nblk - base);
+        for (uint32_t d = 1; d < span; d <<= 1) {
             unsigned long long nv = s_v[cur][tid];
             uint32_t nr = s_r[cur][tid];
             if (tid >= d && !nr) {
@@ -766,80 +770,92 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
     slot[nwp * kSlotStride] = 0;
 }
 
-template <bool kBatch>
+template <bool kBatch, bool kAligned>
 __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
     __shared__ uint32_t s_slot[kSlotWords * kSlotStride];  // private slots; tile bytes (generic path)
     __shared__ unsigned long long s_code[256];
     __shared__ uint16_t s_code16[256];
     __shared__ uint8_t s_code8[256];
     __shared__ uint8_t s_len[256];
-    __shared__ uint8_t s_prev[32];
+    __shared__ uint32_t s_prev4[8];  // the 32 input bytes before the tile
     __shared__ uint32_t s_L[kEncThreads];
     __shared__ uint32_t s_wsum[kEncWaves];
+    const uint8_t* s_prev = reinterpret_cast<const uint8_t*>(s_prev4);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const huff_dcb* loaded = nullptr;
     bool fast = true;
     uint32_t group = 1;
-    uint64_t blkDone = 0;           // scan blocks already summed into blkPrefix
-    unsigned long long blkPrefix = 0;
 
     auto fileOf = [&](uint64_t tile) -> const FileDesc& {
         if constexpr (kBatch) return a.files[a.tile_file[tile]];
         else return a.one;
     };
-    auto loadUnit = [&](uint64_t tile, uint4& y0, uint4& y1, uint4& y2, uint4& y3) {
+    // Everything a tile needs from memory is requested one tile ahead, by a
+    // fixed sequence of loads with no branch: the thread's 64 bytes, the 32
+    // bytes before the tile (lanes 0..7), the tile's offset inside its scan
+    // block and the carry of its block.  They are first used in the next
+    // iteration, so the wait for them does not fall right behind their issue.
+    struct Pre {
+        uint4 x0, x1, x2, x3;
+        uint32_t before, local;
+        unsigned long long carry;
+    };
+    auto fetch = [&](uint64_t tile, Pre& p) {
         const FileDesc& d = fileOf(tile);
-        const uint64_t q = (tile - d.first) * (uint64_t)kEncTile + (uint64_t)tid * kEncUnit;
-        const bool al = ((uintptr_t)d.in & 15u) == 0;
-        y0 = load16(d.in, q, d.n, al);
-        y1 = load16(d.in, q + 16, d.n, al);
-        y2 = load16(d.in, q + 32, d.n, al);
-        y3 = load16(d.in, q + 48, d.n, al);
-    };
-    // A tile's first stream bit: one stream, the sum of the block totals
-    // before its scan block + its offset inside the block; a batch, its
-    // offset inside block and file + the carry of its block when the file
-    // began before the block.  Both are fetched one tile ahead with vector
-    // loads: a scalar load would share its wait counter with the LDS table
-    // lookups and stall them for a memory round trip.
-    auto tileStart = [&](uint64_t tile, uint64_t& done, unsigned long long& prefix) -> uint64_t {
-        const uint64_t blk = tile / kScanTiles;
-        uint32_t lane0 = (uint32_t)(tid >> 10);  // 0, but not known to the compiler: forces vector loads
-        asm volatile("" : "+v"(lane0));
-        if constexpr (kBatch) {
-            const FileDesc& d = fileOf(tile);
-            const unsigned long long carry = d.first <= blk * kScanTiles ? a.blk_carry[blk + lane0] : 0ull;
-            return carry + a.tile_local[tile + lane0];
+        const uint64_t j = tile - d.first;
+        const uint64_t q = j * (uint64_t)kEncTile + (uint64_t)tid * kEncUnit;
+        if constexpr (kAligned) {
+            // whole aligned 16-byte blocks: a block that holds a byte of the
+            // file lies in a page of the file; a block wholly past the end is
+            // replaced by block 0 (its bytes are not used)
+            auto blk = [&](uint64_t at) { return *reinterpret_cast<const uint4*>(d.in + (at < d.n ? at : 0)); };
+            p.x0 = blk(q);
+            p.x1 = blk(q + 16);
+            p.x2 = blk(q + 32);
+            p.x3 = blk(q + 48);
+            const uint64_t bo = j > 0 && tid < 8 ? j * (uint64_t)kEncTile - 32 + 4 * tid : 0;
+            p.before = *reinterpret_cast<const uint32_t*>(d.in + bo);
         } else {
-            for (; done < blk; ++done) prefix += a.blk_total[done + lane0];
-            return prefix + a.tile_local[tile + lane0];
+            p.x0 = load16(d.in, q, d.n, false);
+            p.x1 = load16(d.in, q + 16, d.n, false);
+            p.x2 = load16(d.in, q + 32, d.n, false);
+            p.x3 = load16(d.in, q + 48, d.n, false);
+            p.before = 0;
+            if (j > 0 && tid < 8) {
+                const uint8_t* bp = d.in + j * (uint64_t)kEncTile - 32 + 4 * tid;
+                p.before = (uint32_t)bp[0] | (uint32_t)bp[1] << 8 | (uint32_t)bp[2] << 16 | (uint32_t)bp[3] << 24;
+            }
         }
+        // vector loads (an index the compiler cannot see is uniform): a
+        // scalar load would share its wait counter with the LDS lookups
+        uint32_t lane0 = (uint32_t)(tid >> 10);
+        asm volatile("" : "+v"(lane0));
+        const uint64_t blk = tile / kScanTiles;
+        p.local = a.tile_local[tile + lane0];
+        // blk_carry[0] is 0: it stands in when the file begins inside the block
+        p.carry = a.blk_carry[(d.first <= blk * kScanTiles ? blk : 0) + lane0];
     };
-    uint64_t g = blockIdx.x;
-    uint4 x0 = make_uint4(0, 0, 0, 0), x1 = x0, x2 = x0, x3 = x0;
-    uint64_t Scur = 0;
-    if (g < a.ntiles) {
-        loadUnit(g, x0, x1, x2, x3);
-        Scur = tileStart(g, blkDone, blkPrefix);
-    }
-    for (; g < a.ntiles; g += gridDim.x) {
+    Pre cur;
+    cur.x0 = cur.x1 = cur.x2 = cur.x3 = make_uint4(0, 0, 0, 0);
+    cur.before = cur.local = 0;
+    cur.carry = 0;
+    if ((uint64_t)blockIdx.x < a.ntiles) fetch(blockIdx.x, cur);
+    for (uint64_t g = blockIdx.x; g < a.ntiles; g += gridDim.x) {
         const FileDesc& f = fileOf(g);
         const uint64_t j = g - f.first;
         const uint64_t n = f.n;
         const uint64_t tstart = j * (uint64_t)kEncTile;
         const uint64_t q0 = tstart + (uint64_t)tid * kEncUnit;
         const uint32_t nv = q0 >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q0);
-        // the next tile's bytes are requested now and used next iteration
+        const uint4 x0 = cur.x0, x1 = cur.x1, x2 = cur.x2, x3 = cur.x3;
+        const uint32_t prev4 = cur.before;
+        const uint64_t S = cur.carry + cur.local;  // the tile's first stream bit
+        // the next tile's loads: unconditional (the last tile re-reads itself)
         const uint64_t gn = g + gridDim.x;
-        uint4 y0 = make_uint4(0, 0, 0, 0), y1 = y0, y2 = y0, y3 = y0;
-        uint64_t Snext = 0;
-        if (gn < a.ntiles) {
-            loadUnit(gn, y0, y1, y2, y3);
-            Snext = tileStart(gn, blkDone, blkPrefix);
-        }
+        fetch(gn < a.ntiles ? gn : g, cur);
         __syncthreads();  // the previous tile is done with the LDS slots and tables
-        if (tid < 32 && j > 0) s_prev[tid] = f.in[tstart - 32 + tid];
+        if (tid < 8) s_prev4[tid] = prev4;
         if (f.cb != loaded) {
             const uint32_t maxLen = f.cb->max_len;
             fast = maxLen <= 16;
@@ -854,7 +870,6 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
             loaded = f.cb;
             __syncthreads();
         }
-        const uint64_t S = Scur;  // the tile's first stream bit
 
         // 1) pack into the private slot (fast) or count bits (generic)
         uint32_t L = 0, nwp = 0, bad = 0;
@@ -1020,17 +1035,17 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
             }
             if (lastThread && na && w < f.nwords) f.words[w] = (uint32_t)(acc << (32 - na));
         }
-        x0 = y0;
-        x1 = y1;
-        x2 = y2;
-        x3 = y3;
-        Scur = Snext;
     }
 }
 
 hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s) {
-    if (a.files) hipLaunchKernelGGL(k_encode<true>, dim3(grid), dim3(kEncThreads), 0, s, a);
-    else hipLaunchKernelGGL(k_encode<false>, dim3(grid), dim3(kEncThreads), 0, s, a);
+    if (a.files) {
+        if (a.aligned) hipLaunchKernelGGL((k_encode<true, true>), dim3(grid), dim3(kEncThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_encode<true, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
+    } else {
+        if (a.aligned) hipLaunchKernelGGL((k_encode<false, true>), dim3(grid), dim3(kEncThreads), 0, s, a);
+        else hipLaunchKernelGGL((k_encode<false, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -37,6 +37,7 @@ struct huff_batch {
     int device = 0;              // ctx's device (destroy may run after the context is gone)
     uint32_t nfiles = 0, chunk_size = 0, sub_size = 0;
     uint64_t ntiles = 0, nitems = 0;
+    bool aligned = true;         // every input 16-byte aligned
     bool can_decode = false;     // every non-empty file has an output buffer
     huff::FileDesc* d_enc = nullptr;   // [nfiles], first = first tile
     huff::FileDesc* d_dec = nullptr;   // [nfiles], first = first decode lane (256-aligned)
@@ -81,6 +82,7 @@ struct BatchTables {
     std::vector<FileDesc> dec;       // first = first decode lane (kDecBatchBlock-aligned)
     std::vector<uint32_t> tile_file; // tile -> file
     uint64_t ntiles = 0, nitems = 0;
+    bool aligned = true;             // every input 16-byte aligned
     bool can_decode = true;          // every non-empty file has an output buffer
 };
 

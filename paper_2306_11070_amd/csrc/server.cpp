@@ -363,6 +363,7 @@ bool huff_server::launch(Slot& sl) {
         pd.nfiles = (uint32_t)df.size();
         pd.nitems = dt.nitems;
         pd.can_decode = dt.can_decode;
+        pc.aligned = ct.aligned;
         pd.d_dec = d_dec;
         if (st == HUFF_OK && pc.nfiles) st = batch_launch(&pc, HUFF_OP_COMPRESS, s);
         if (st == HUFF_OK && pc.nfiles) st = hip_status(launch_gather_u64(d_lenptr, d_len, pc.nfiles, s));
