@@ -1188,6 +1188,44 @@ struct LdsReader {
 };
 
 // One symbol from a reader whose window holds >= 32 valid bits after refill.
+// Reader for the table-only decoder over words staged in LDS: every k
+// symbols it re-reads the 64 stream bits at its position and otherwise only
+// shifts.  A window read at most 31 bits into a word holds at least 33 bits
+// ahead of the position, enough for k codes of at most maxLen bits and the
+// lutBits peek of the last of them when (k - 1) * maxLen + lutBits <= 33.
+struct WinReader {
+    const uint32_t* s;
+    uint32_t last;     // index of the buffer's last word
+    uint32_t pos;      // bit position of the window's first bit
+    uint32_t cons;     // bits consumed from the window
+    uint32_t c, k;     // symbols taken from the window, symbols per window
+    uint64_t win;
+    __device__ __forceinline__ void init(const uint32_t* s_, uint32_t lim, uint32_t bit, uint32_t k_) {
+        s = s_;
+        last = lim - 1;
+        pos = bit;
+        cons = 0;
+        c = k = k_;
+        win = 0;
+    }
+    __device__ __forceinline__ uint32_t next(const DecTables& t, uint32_t lutBits, uint32_t& emin) {
+        if (c == k) {
+            pos += cons;
+            const uint32_t w = min(pos >> 5, last - 1);
+            win = (((uint64_t)s[w] << 32) | s[w + 1]) << (pos & 31);
+            cons = 0;
+            c = 0;
+        }
+        const uint32_t e = t.lut[(uint32_t)(win >> 32) >> (32 - lutBits)];
+        emin = min(emin, e);
+        const uint32_t len = e >> 8;
+        win <<= len;
+        cons += len;
+        ++c;
+        return e & 0xffu;
+    }
+};
+
 // kFits: every code is at most lutBits long, so the table alone decodes; a
 // table entry of 0 (no code matches) is then kept in emin and reported by
 // the caller instead of being branched on per symbol.
@@ -1208,6 +1246,14 @@ __device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lut
     r.avail -= len;
     used += len;
     return e & 0xffu;
+}
+
+// The windowed reader decodes from the table alone; bits used are counted by
+// its position, not here.
+template <bool kFits, typename U>
+__device__ __forceinline__ uint32_t dec1(WinReader& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+                                         U& used, uint32_t& emin) {
+    return r.next(t, lutBits, emin);
 }
 
 constexpr int kDecLine = 64;  // bytes a decode lane stores together
@@ -1425,9 +1471,17 @@ __global__ __launch_bounds__(256) void k_decode_staged(DecArgs a) {
     uint32_t used = 0;
     constexpr int kLine = S < kDecLine ? S : kDecLine;
     if (staged) {
-        LdsReader rd;
-        rd.init(s_in[wave], kInWords, (uint32_t)(start - (base << 5)));
-        dec_run<kLine>(rd, t, lutBits, maxLen, bad, used, out, nsym);
+        const uint32_t bit0 = (uint32_t)(start - (base << 5));
+        if (maxLen <= lutBits) {
+            WinReader rd;
+            rd.init(s_in[wave], kInWords, bit0, (33u - lutBits) / maxLen + 1);
+            dec_run_k<kLine, true>(rd, t, lutBits, maxLen, bad, used, out, nsym);
+            used = rd.pos + rd.cons - bit0;
+        } else {
+            LdsReader rd;
+            rd.init(s_in[wave], kInWords, bit0);
+            dec_run_k<kLine, false>(rd, t, lutBits, maxLen, bad, used, out, nsym);
+        }
     } else {
         BitReader rd;
         rd.init(f.words, f.nwords, start);
