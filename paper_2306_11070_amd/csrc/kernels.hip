@@ -211,34 +211,6 @@ hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s) {
 }
 
 // =============================================================== codebook
-__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m) {
-    const uint32_t lo = __shfl_xor((uint32_t)v, m, 64), hi = __shfl_xor((uint32_t)(v >> 32), m, 64);
-    return ((uint64_t)hi << 32) | lo;
-}
-
-// Bitonic sort of 256 u64 keys, one per thread of a 256-thread workgroup;
-// thread t returns the t-th smallest.  Exchanges inside a wave use lane
-// shuffles; only the three stages that cross waves go through LDS.
-__device__ uint64_t sort256(uint64_t key, unsigned long long* tmp) {
-    const uint32_t t = threadIdx.x;
-    for (uint32_t k = 2; k <= 256; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            uint64_t other;
-            if (j >= 64) {
-                tmp[t] = key;
-                __syncthreads();
-                other = tmp[t ^ j];
-                __syncthreads();
-            } else {
-                other = shfl_xor_u64(key, (int)j);
-            }
-            const bool keepMin = ((t & j) == 0) == ((t & k) == 0);
-            key = keepMin ? (key < other ? key : other) : (key < other ? other : key);
-        }
-    }
-    return key;
-}
-
 // One workgroup of 256 threads; thread v owns byte value v.
 //
 // Code lengths follow the merge rule (two smallest (weight, id) nodes ->
@@ -252,7 +224,7 @@ __device__ uint64_t sort256(uint64_t key, unsigned long long* tmp) {
 // newer one.
 __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
     __shared__ unsigned long long s_w[512];  // node weights: sorted leaves [0,K), internal nodes [K, 2K-1)
-    __shared__ unsigned long long s_tmp[256];
+    __shared__ __align__(16) unsigned long long s_tmp[256];  // sort keys
     __shared__ uint16_t s_par[512], s_m[512];
     __shared__ uint16_t s_d[512], s_p[512];
     __shared__ uint8_t s_sym[256];            // leaf rank -> byte
@@ -263,6 +235,7 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
     __shared__ uint32_t s_wcnt[64][kCbThreads / 64];  // bytes of each length, per wave
     __shared__ unsigned long long s_red_t[kCbThreads / 64], s_red_n[kCbThreads / 64];
     __shared__ uint32_t s_red_m[kCbThreads / 64];
+    __shared__ uint32_t s_rc[kCbThreads / 64][2];  // per-wave counts of a merge round
     const uint32_t v = threadIdx.x;
     uint64_t h = 0;
     uint32_t myLen = 0;
@@ -298,13 +271,24 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
             h = a.hist[v];
         }
         if (__syncthreads_or(h >> 56)) status = HUFF_E_INVAL;  // counts must fit the sort key
-        const uint32_t K = (uint32_t)__syncthreads_count(h != 0);
-        // leaves in (count, value) order; absent bytes sort first as key 0
-        const uint64_t key = sort256(h && status == HUFF_OK ? (h << 8) | v : 0ull, s_tmp);
-        const uint32_t off = 256 - K;
-        if (v >= off) {
-            s_w[v - off] = key >> 8;
-            s_sym[v - off] = (uint8_t)(key & 0xffu);
+        // leaves in (count, value) order: a present byte's rank is the number
+        // of smaller keys (absent bytes are key 0, below every present one;
+        // present keys are distinct), counted against all 256 keys in LDS
+        const uint64_t key = h && status == HUFF_OK ? (h << 8) | v : 0ull;
+        s_tmp[v] = key;
+        const uint32_t K = (uint32_t)__syncthreads_count(key != 0);
+        if (key) {
+            uint32_t r0 = 0, r1 = 0;
+            const ulonglong2* k2 = reinterpret_cast<const ulonglong2*>(s_tmp);
+#pragma unroll 8
+            for (int u = 0; u < 128; ++u) {
+                const ulonglong2 p = k2[u];
+                r0 += p.x < key ? 1u : 0u;
+                r1 += p.y < key ? 1u : 0u;
+            }
+            const uint32_t i = r0 + r1 - (256 - K);
+            s_w[i] = h;
+            s_sym[i] = (uint8_t)v;
         }
         __syncthreads();
         if (status != HUFF_OK) {
@@ -312,7 +296,9 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
         } else if (K == 1) {
             myLen = h ? 1u : 0u;
         } else if (K >= 2) {
+            const uint32_t lane = v & 63, wave = v >> 6;
             uint32_t li = 0, qi = 0, m = 0;  // leaf head, internal head, internal nodes made
+            uint32_t rounds = 0;
             while (m < K - 1) {
                 // s0: sum of the two smallest queued nodes (leaf first on ties)
                 const uint64_t kInf = ~0ull;
@@ -323,8 +309,21 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
                 else s0 = i0 + (l0 <= i1 ? l0 : i1);
                 const bool leafIn = li + v < K && s_w[li + v] <= s0;
                 const bool intIn = qi + v < m && s_w[K + qi + v] <= s0;
-                const uint32_t cL = (uint32_t)__syncthreads_count(leafIn);
-                const uint32_t cI = (uint32_t)__syncthreads_count(intIn);
+                // both counts with one barrier: per-wave ballots, then a sum
+                {
+                    const uint64_t bl = __ballot(leafIn), bi = __ballot(intIn);
+                    if (lane == 0) {
+                        s_rc[wave][0] = (uint32_t)__popcll(bl);
+                        s_rc[wave][1] = (uint32_t)__popcll(bi);
+                    }
+                }
+                __syncthreads();
+                uint32_t cL = 0, cI = 0;
+#pragma unroll
+                for (int w = 0; w < kCbThreads / 64; ++w) {
+                    cL += s_rc[w][0];
+                    cI += s_rc[w][1];
+                }
                 const uint32_t pairs = (cL + cI) >> 1;
                 // merged position of each node taking part
                 // both binary searches in one loop, so that their LDS reads overlap:
@@ -357,6 +356,7 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
                 li += nl;
                 qi += 2 * pairs - nl;
                 m += pairs;
+                ++rounds;
             }
             // depths by pointer jumping: d = distance to p, p -> p's ancestor
             const uint32_t nodes = 2 * K - 1, root = nodes - 1;
@@ -365,7 +365,10 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
                 s_p[i] = i == root ? root : s_par[i];
             }
             __syncthreads();
-            for (int it = 0; it < 8; ++it) {
+            // the tree is at most `rounds` deep (a round pairs only nodes made
+            // before it), so ceil(log2(rounds + 1)) doublings reach the root
+            const int jumps = 32 - __clz(rounds);
+            for (int it = 0; it < jumps; ++it) {
                 uint16_t nd[2] = {0, 0}, np[2] = {0, 0};
 #pragma unroll
                 for (int t = 0; t < 2; ++t) {
