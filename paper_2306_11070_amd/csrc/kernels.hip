@@ -32,6 +32,17 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
 // release/acquire on all memory), which would drain the next tile's prefetch
 // and the current tile's stores at each barrier.  Used where the threads of
 // a workgroup share data through LDS alone.
+// Inclusive prefix sum of a u64 across the 64 lanes of a wave.
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t lo = __shfl_up((uint32_t)x, d, 64), hi = __shfl_up((uint32_t)(x >> 32), d, 64);
+        if (lane >= (uint32_t)d) x += ((uint64_t)hi << 32) | lo;
+    }
+    return x;
+}
+
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -441,15 +452,14 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
     }
     __syncthreads();
     if (v < 64) {
-        // first canonical code of length v: sum over j < v of count[j] * 2^(v-j)
-        uint32_t fidx = 0;
-        uint64_t fc = 0;
-        for (uint32_t j = 1; j < v; ++j) {
-            fidx += s_cnt[j];
-            fc += (uint64_t)s_cnt[j] << (v - j);
-        }
-        s_fidx[v] = fidx;
-        s_first[v] = fc;
+        // wave 0, lane v = length v: fidx = bytes with shorter codes; first
+        // canonical code of length v = sum over j < v of count[j] * 2^(v-j),
+        // taken from the Kraft sums F(v) = sum over j < v of count[j] * 2^(63-j)
+        // (at most 2^63: every code reaching here satisfies Kraft's inequality)
+        const uint32_t c = s_cnt[v];
+        s_fidx[v] = wave_incl_scan(c) - c;
+        const uint64_t kv = v >= 1 ? (uint64_t)c << (63 - v) : 0ull;
+        s_first[v] = (wave_incl_scan_u64(kv) - kv) >> (63 - v);
     }
     __syncthreads();
     // the byte's place in (length, value) order and its canonical code
