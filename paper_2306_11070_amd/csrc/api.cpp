@@ -278,9 +278,11 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
             ta.cb = d_cb;
             ta.ntiles = ntiles;
             ta.tile_bits = c->tile_bits;
+            ta.status = d_status;
+            ta.err = c->status;
             st = hip_status(launch_tile_bits_hist(ta, s));
         } else {
-            st = hip_status(launch_tile_bits(d_in, n, d_cb, c->tile_bits, s));
+            st = hip_status(launch_tile_bits(d_in, n, d_cb, c->tile_bits, d_status, c->status, s));
         }
         if (st == HUFF_OK) {
             ScanArgs sa;
@@ -634,6 +636,7 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
     ta.tile_file = b->d_tile_file;
     ta.ntiles = b->ntiles;
     ta.tile_bits = b->d_tile_local;
+    ta.err = c->status;
     huff_status st = hip_status(launch_tile_bits_hist(ta, s));
     if (st != HUFF_OK) return st;
     ScanArgs sa;

@@ -75,6 +75,8 @@ struct TileBitsArgs {
     const uint32_t* tile_file;  // ... and file index of every tile
     uint64_t ntiles;
     uint32_t* tile_bits;        // out: code bits of each tile
+    int32_t* status;            // single file: its status word (or null) ...
+    int32_t* err;               // ... fallback: the context's (batch: files[i].status, else this)
 };
 
 struct ScanArgs {
@@ -125,7 +127,8 @@ struct CbArgs {
 hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s);
 hipError_t launch_codebook(const CbArgs& a, uint32_t nblocks, hipStream_t s);
-hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, uint32_t* tile_bits, hipStream_t s);
+hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, uint32_t* tile_bits, int32_t* status,
+                            int32_t* err, hipStream_t s);
 hipError_t launch_tile_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_tile_bits_hist(const TileBitsArgs& a, hipStream_t s);
 hipError_t launch_blk_scan(const unsigned long long* blk_tail, unsigned long long* blk_carry, uint64_t nblk,

@@ -523,7 +523,7 @@ hipError_t launch_codebook(const CbArgs& a, uint32_t nblocks, hipStream_t s) {
 constexpr int kScanTiles = kScanTilesPerBlock;
 
 __global__ __launch_bounds__(kEncThreads) void k_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb,
-                                                            uint32_t* tile_bits) {
+                                                            uint32_t* tile_bits, int32_t* status, int32_t* err) {
     __shared__ uint8_t s_len[256];
     __shared__ uint32_t s_sum[kEncThreads / 64];
     const uint32_t tid = threadIdx.x;
@@ -535,10 +535,16 @@ __global__ __launch_bounds__(kEncThreads) void k_tile_bits(const uint8_t* in, ui
 #pragma unroll
     for (int k = 0; k < kEncUnit / 16; ++k) x[k] = load16(in, q + 16 * k, n, aligned);
     __syncthreads();
-    uint32_t sum = 0;
+    uint32_t sum = 0, missing = 0;
     const uint32_t nv = q >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q);
 #pragma unroll
-    for (int i = 0; i < kEncUnit; ++i) sum += (uint32_t)i < nv ? s_len[byte_of(x[i >> 4], i & 15)] : 0u;
+    for (int i = 0; i < kEncUnit; ++i) {
+        const uint32_t l = (uint32_t)i < nv ? s_len[byte_of(x[i >> 4], i & 15)] : 1u;
+        sum += (uint32_t)i < nv ? l : 0u;
+        missing |= l == 0 ? 1u : 0u;
+    }
+    // a byte that has no code (the encoder itself does not check)
+    if (missing) report(status, err, HUFF_E_INVAL);
     sum = (uint32_t)wave_sum_u64(sum);
     if ((tid & 63) == 0) s_sum[tid >> 6] = sum;
     __syncthreads();
@@ -564,6 +570,10 @@ __global__ __launch_bounds__(256) void k_tile_bits_hist(TileBitsArgs a) {
     const uint32_t l4 = reinterpret_cast<const uint32_t*>(cb->len)[lane];
     uint32_t bits = (h.x & 0xffffu) * (l4 & 0xffu) + (h.x >> 16) * ((l4 >> 8) & 0xffu) +
                     (h.y & 0xffffu) * ((l4 >> 16) & 0xffu) + (h.y >> 16) * (l4 >> 24);
+    // a byte that occurs but has no code (the encoder itself does not check)
+    const bool missing = ((h.x & 0xffffu) && !(l4 & 0xffu)) || ((h.x >> 16) && !(l4 & 0xff00u)) ||
+                         ((h.y & 0xffffu) && !(l4 & 0xff0000u)) || ((h.y >> 16) && !(l4 & 0xff000000u));
+    if (missing) report(kBatch ? a.files[a.tile_file[t]].status : a.status, a.err, HUFF_E_INVAL);
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) bits += __shfl_xor(bits, d, 64);
     if (lane == 0) a.tile_bits[t] = bits;
@@ -684,9 +694,10 @@ __global__ __launch_bounds__(1024) void k_blk_scan(const unsigned long long* tai
     }
 }
 
-hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, uint32_t* tile_bits, hipStream_t s) {
+hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, uint32_t* tile_bits, int32_t* status,
+                            int32_t* err, hipStream_t s) {
     const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
-    hipLaunchKernelGGL(k_tile_bits, dim3((uint32_t)ntiles), dim3(kEncThreads), 0, s, in, n, cb, tile_bits);
+    hipLaunchKernelGGL(k_tile_bits, dim3((uint32_t)ntiles), dim3(kEncThreads), 0, s, in, n, cb, tile_bits, status, err);
     return hipGetLastError();
 }
 
@@ -734,8 +745,7 @@ __device__ __forceinline__ uint32_t byte64(const uint4& a, const uint4& b, const
 template <int G>
 __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const uint4 x2, const uint4 x3,
                                           const uint8_t* s_len, const uint8_t* s_code8, const uint16_t* s_code16,
-                                          uint32_t* slot, uint32_t& L, uint32_t& nwp, uint32_t& bad,
-                                          uint32_t nv = kEncUnit) {
+                                          uint32_t* slot, uint32_t& L, uint32_t& nwp, uint32_t nv = kEncUnit) {
     uint64_t acc = 0;
     uint32_t na = 0, wi = 0;
     auto emit = [&]() {
@@ -749,7 +759,6 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
         for (uint32_t i = 0; i < nv; ++i) {
             const uint32_t v = byte64(x0, x1, x2, x3, (int)i);
             const uint32_t l = s_len[v];
-            bad |= l == 0;
             acc = (acc << l) | s_code16[v];
             na += l;
             emit();
@@ -764,7 +773,6 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
                     const uint32_t v = byte64(x0, x1, x2, x3, i0 + k);
                     const uint32_t l = s_len[v];
                     const uint32_t c = G == 4 ? (uint32_t)s_code8[v] : (uint32_t)s_code16[v];
-                    bad |= l == 0 ? 1u : 0u;
                     g = (g << l) | c;
                     gl += l;
                 }
@@ -885,7 +893,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
         }
 
         // 1) pack into the private slot (fast) or count bits (generic)
-        uint32_t L = 0, nwp = 0, bad = 0;
+        uint32_t L = 0, nwp = 0;
         if (fast) {
             uint32_t* slot = s_slot + tid;  // stride kSlotStride
             if (nv == kEncUnit) {
@@ -895,16 +903,16 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
                 asm volatile("" : "+v"(z0.x), "+v"(z0.y), "+v"(z0.z), "+v"(z0.w), "+v"(z1.x), "+v"(z1.y), "+v"(z1.z), "+v"(z1.w)::"memory");
                 asm volatile("" : "+v"(z2.x), "+v"(z2.y), "+v"(z2.z), "+v"(z2.w), "+v"(z3.x), "+v"(z3.y), "+v"(z3.z), "+v"(z3.w)::"memory");
                 if (group == 4) {
-                    pack_unit<4>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp, bad);
+                    pack_unit<4>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp);
                 } else if (group == 3) {
                     asm volatile("" : "+v"(z0.x), "+v"(z1.x), "+v"(z2.x), "+v"(z3.x)::"memory");
-                    pack_unit<3>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp, bad);
+                    pack_unit<3>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp);
                 } else {
                     asm volatile("" : "+v"(z0.y), "+v"(z1.y), "+v"(z2.y), "+v"(z3.y)::"memory");
-                    pack_unit<2>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp, bad);
+                    pack_unit<2>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp);
                 }
             } else {
-                pack_unit<1>(x0, x1, x2, x3, s_len, s_code8, s_code16, slot, L, nwp, bad, nv);
+                pack_unit<1>(x0, x1, x2, x3, s_len, s_code8, s_code16, slot, L, nwp, nv);
             }
         } else {
             uint4* in4 = reinterpret_cast<uint4*>(s_slot) + 4 * tid;
@@ -912,13 +920,8 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
             in4[1] = x1;
             in4[2] = x2;
             in4[3] = x3;
-            for (uint32_t i = 0; i < nv; ++i) {
-                const uint32_t l = s_len[byte64(x0, x1, x2, x3, (int)i)];
-                bad |= l == 0;
-                L += l;
-            }
+            for (uint32_t i = 0; i < nv; ++i) L += s_len[byte64(x0, x1, x2, x3, (int)i)];
         }
-        if (bad) report(f.status, a.err, HUFF_E_INVAL);
 
         // 2) workgroup exclusive scan of per-thread bit counts
         s_L[tid] = L;
