@@ -18,7 +18,7 @@ namespace {
 huff_params defaults(int num_cus) {
     huff_params p;
     p.enc_blocks_per_cu = 3;  // LDS allows three encode workgroups per CU
-    p.hist_blocks = (uint32_t)num_cus * 2;
+    p.hist_blocks = (uint32_t)num_cus * 4;
     p.hist_depth = 16;
     p.dec_block = 256;
     return p;
