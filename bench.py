@@ -132,6 +132,41 @@ def batch_leg(P, codec, nfiles: int, reps: int):
             "graph": True, "roundtrip_ok": bool(ok), "datagen_s": round(gen_s, 1)}
 
 
+def segments_leg(P, codec, x, T_global: int, seg: int, sub: int, reps: int):
+    """The same input with a codebook per segment (one batch plan over the
+    segments, graph replays), against the global codebook's size."""
+    import numpy as np
+    import torch
+
+    sg = P.Segments(codec, x, seg, seg, sub)
+    sg.compress(graph=True)
+    sg.decode(graph=True)
+    torch.cuda.synchronize()
+    ok = all(int(v) == 0 for v in sg.status.cpu().tolist()) and bool(torch.equal(sg.out, x))
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    tc, td = [], []
+    for _ in range(reps):
+        ev[0].record()
+        sg.compress(graph=True)
+        ev[1].record()
+        sg.decode(graph=True)
+        ev[2].record()
+        torch.cuda.synchronize()
+        tc.append(ev[0].elapsed_time(ev[1]))
+        td.append(ev[1].elapsed_time(ev[2]))
+    bits = sum(sg.segment_bits())
+    n = x.numel()
+    ms = float(np.median(tc)) + float(np.median(td))
+    # stored size: payload plus the 256 code lengths of each codebook
+    size_seg = bits / 8 + 256 * sg.nseg
+    size_glb = T_global / 8 + 256
+    sg.close()
+    return {"segment_bytes": seg, "n_segments": sg.nseg, "compress_ms": round(float(np.median(tc)), 4),
+            "decode_ms": round(float(np.median(td)), 4), "GBps": round(n / (ms * 1e-3) / 1e9, 2),
+            "bits_per_byte": round(bits / n, 4), "size_vs_global_codebook": round(size_seg / size_glb, 5),
+            "graph": True, "roundtrip_ok": ok}
+
+
 def _dev_equal(pa: int, pb: int, nbytes: int) -> bool:
     """Compares two device byte ranges (copies both to the host)."""
     import ctypes
@@ -234,12 +269,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="markov_45MiB", choices=sorted(WORKLOADS))
     ap.add_argument("--sub", type=int, default=None, help="decode sub-block bytes (0: chunk index only)")
-    ap.add_argument("--cpu-passes", type=int, default=4)
+    ap.add_argument("--cpu-passes", type=int, default=8)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true", help="also run the plain copy kernel (counter calibration)")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-file batch leg")
     ap.add_argument("--batch-files", type=int, default=4096)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
+    ap.add_argument("--no-segments", action="store_true", help="skip the per-segment codebook leg")
+    ap.add_argument("--segment", type=int, default=256 << 10, help="segment bytes of the per-segment codebook leg")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-pool", type=int, default=384)
     args = ap.parse_args()
@@ -388,6 +425,8 @@ def main():
                                 "sample": f"the whole {n}-byte workload, histogram+codebook+encode+decode, "
                                           f"{passes} passes averaged (plain serial C, one thread)"}
         line["bitexact_vs_oracle"] = bitexact
+    if not args.no_segments:
+        line["segments"] = segments_leg(P, codec, x, T, args.segment, sub, 20)
     if not args.no_batch:
         line["batch"] = batch_leg(P, codec, args.batch_files, 10)
     if not args.no_serve:

@@ -18,7 +18,7 @@ from ._abi import (HuffCodebook, HuffDcb, HuffFile, HuffParams, HuffRequest, Huf
                    HuffStreamInfo, ERRORS, HuffError, lib, load, HUFF_OP_COMPRESS, HUFF_OP_ENCODE, HUFF_OP_DECODE,
                    HUFF_E_AGAIN)
 
-__all__ = ["Codec", "Batch", "Server", "batch_buffers", "HuffError", "build_codebook", "encoded_bits", "dcb_to_host", "load", "DCB_BYTES"]
+__all__ = ["Codec", "Batch", "Segments", "Server", "batch_buffers", "HuffError", "build_codebook", "encoded_bits", "dcb_to_host", "load", "DCB_BYTES"]
 
 DCB_BYTES = ctypes.sizeof(HuffDcb)
 
@@ -295,6 +295,68 @@ def batch_buffers(codec: "Codec", inputs: list, chunk_size: int, sub_size: int =
             f["out"] = torch.empty(n, dtype=torch.uint8, device=dev)
         files.append(f)
     return files
+
+
+class Segments:
+    """Per-segment codebooks within one stream (Method 2 as the paper states
+    it: the input cut into segments, each coded with a tree of its own, the
+    coded segments kept in segment order).  One batch plan over the segments
+    does the work; its outputs live in single allocations, one fixed-size
+    region per segment: ``cb`` [nseg, DCB_BYTES], ``words`` [nseg, wcap],
+    ``chunk_off`` [nseg, nch + 1], ``sub_lo`` [nseg, nsub + 1], ``hist``
+    [nseg, 256], ``status`` [nseg] and ``out`` (n bytes, decode output).
+    Chunks and sub-blocks restart at every segment.  ``seg_size`` is a
+    multiple of 16 so that every segment of a 16-byte aligned input is too.
+    """
+
+    def __init__(self, codec: "Codec", x, seg_size: int, chunk_size: int, sub_size: int = 0, decode: bool = True):
+        torch = _torch()
+        if seg_size <= 0 or seg_size % 16:
+            raise ValueError("seg_size must be a positive multiple of 16")
+        x = codec._u8(x)
+        n = x.numel()
+        dev = codec.device
+        self.n, self.seg_size = n, seg_size
+        self.nseg = nseg = (n + seg_size - 1) // seg_size
+        nch = (seg_size + chunk_size - 1) // chunk_size
+        wcap = ((seg_size * 16 + 31) // 32 + 8 + 3) // 4 * 4  # 16 bits per byte, 16-byte rows
+        self.cb = torch.empty((max(1, nseg), DCB_BYTES), dtype=torch.uint8, device=dev)
+        self.words = torch.empty((max(1, nseg), wcap), dtype=torch.int32, device=dev)
+        self.chunk_off = torch.empty((max(1, nseg), nch + 1), dtype=torch.int64, device=dev)
+        self.sub_lo = None
+        if sub_size:
+            nsub = (seg_size + sub_size - 1) // sub_size
+            self.sub_lo = torch.empty((max(1, nseg), nsub + 1), dtype=torch.int32, device=dev)
+        self.hist = torch.empty((max(1, nseg), 256), dtype=torch.int64, device=dev)
+        self.status = torch.zeros(max(1, nseg), dtype=torch.int32, device=dev)
+        self.out = torch.empty(n, dtype=torch.uint8, device=dev) if decode else None
+        files = []
+        for i in range(nseg):
+            lo, hi = i * seg_size, min(n, (i + 1) * seg_size)
+            f = {"in": x[lo:hi], "n": hi - lo, "cb": self.cb[i], "words": self.words[i],
+                 "chunk_off": self.chunk_off[i, :(hi - lo + chunk_size - 1) // chunk_size + 1],
+                 "hist": self.hist[i], "status": self.status[i:i + 1]}
+            if sub_size:
+                f["sub_lo"] = self.sub_lo[i, :(hi - lo + sub_size - 1) // sub_size + 1]
+            if decode:
+                f["out"] = self.out[lo:hi]
+            files.append(f)
+        self.files = files
+        self.batch = Batch(codec, files, chunk_size, sub_size)
+
+    def compress(self, graph: bool = False, stream=None):
+        self.batch.compress(graph, stream)
+
+    def decode(self, graph: bool = False, stream=None):
+        self.batch.decode(graph, stream)
+
+    def segment_bits(self):
+        """Code bits of every segment: the last entry of its segment index (one copy to the host)."""
+        off = self.chunk_off.cpu()
+        return [int(off[i, f["chunk_off"].numel() - 1]) for i, f in enumerate(self.files)]
+
+    def close(self):
+        self.batch.close()
 
 
 class Server:
