@@ -290,11 +290,9 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
             sa.tile_bits = c->tile_bits;
             sa.ntiles = ntiles;
             sa.tile_local = c->tile_local;
-            sa.blk_tail = c->blk_tail;
+            sa.blk_carry = c->blk_carry;
             st = hip_status(launch_tile_scan(sa, s));
         }
-        if (st == HUFF_OK)
-            st = hip_status(launch_blk_scan(c->blk_tail, c->blk_carry, (ntiles + kScanTilesPerBlock - 1) / kScanTilesPerBlock, s));
     }
     if (st != HUFF_OK) return st;
     EncArgs a;

@@ -58,11 +58,12 @@ struct EncArgs {
     int32_t* err;           // fallback status word
 };
 
-// Tile offsets are a scan in two levels, segmented by file in a batch:
-// k_tile_scan / k_tile_scan_seg scan the tiles of each 1024-tile block,
-// k_blk_scan carries the open file's running total from block to block.
-// blk_tail packs, per block, the bits of its last segment (low 62 bits) with
-// two flags.
+// Tile offsets are a scan in two levels.  One stream: k_tile_scan scans the
+// tiles of each 1024-tile block and sums the bits of all earlier tiles into
+// the block's carry.  A batch: k_tile_scan_seg scans each block restarting at
+// every file, and k_blk_scan carries the open file's running total from
+// block to block; blk_tail packs, per block, the bits of its last segment
+// (low 62 bits) with two flags.
 constexpr unsigned long long kTailStarts = 1ull << 63;  // the block's last segment starts inside the block
 constexpr unsigned long long kTailHead = 1ull << 62;    // a file starts at the block's first tile
 constexpr unsigned long long kTailBits = kTailHead - 1;
@@ -85,7 +86,8 @@ struct ScanArgs {
     const uint32_t* tile_file;  // ... and file index of every tile
     uint64_t ntiles;
     uint32_t* tile_local;
-    unsigned long long* blk_tail;   // last segment of each block, with flags
+    unsigned long long* blk_tail;   // batch: last segment of each block, with flags
+    unsigned long long* blk_carry;  // one stream: bits of all tiles before each block
 };
 
 struct DecArgs {

@@ -514,8 +514,9 @@ hipError_t launch_codebook(const CbArgs& a, uint32_t nblocks, hipStream_t s) {
 // Tile offsets.  A tile's code bits are known before it is encoded: from its
 // u16 histogram (sum of count x length, written by k_hist) or, for a
 // standalone encode, counted by k_tile_bits.  One stream: k_tile_scan turns
-// them into an exclusive prefix inside blocks of kScanTiles tiles plus one
-// total per block.  A batch: the scan restarts at every file; k_tile_scan_seg
+// them into an exclusive prefix inside blocks of kScanTiles tiles, and each
+// block sums the bits of all earlier tiles into its carry.  A batch: the scan
+// restarts at every file; k_tile_scan_seg
 // scans inside the blocks and k_blk_scan carries the running total of the
 // file that is open across a block boundary, so a tile's first bit is
 // tile_local + (carry of its block if its file began before the block).
@@ -588,27 +589,34 @@ hipError_t launch_tile_bits_hist(const TileBitsArgs& a, hipStream_t s) {
 }
 
 // One stream: exclusive scan of the tile bits inside blocks of kScanTiles
-// tiles, one thread per tile, and each block's total (as a block tail).  tile_local may be the
+// tiles, one thread per tile, and each block's carry.  tile_local may be the
 // tile_bits buffer itself (each thread reads its tile's count before it
 // writes that tile's offset).
 __global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
     __shared__ uint32_t s_wsum[kScanTiles / 64];
+    __shared__ unsigned long long s_wcar[kScanTiles / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const uint64_t t = (uint64_t)blockIdx.x * kScanTiles + tid;
+    const uint64_t b0 = (uint64_t)blockIdx.x * kScanTiles;
+    const uint64_t t = b0 + tid;
     const uint32_t bits = t < a.ntiles ? a.tile_bits[t] : 0u;
+    // the block's carry: the bits of every earlier tile, summed here from the
+    // tile counts (a strided read of at most ntiles words per block), so that
+    // one stream needs no separate scan of block totals
+    unsigned long long car = 0;
+    for (uint64_t u = tid; u < b0; u += kScanTiles) car += a.tile_bits[u];
+    car = wave_sum_u64(car);
     const uint32_t incl = wave_incl_scan(bits);
     if (lane == 63) s_wsum[wave] = incl;
+    if (lane == 0) s_wcar[wave] = car;
     __syncthreads();
-    uint32_t before = 0, total = 0;
-    for (int w = 0; w < kScanTiles / 64; ++w) {
-        const uint32_t ws = s_wsum[w];
-        total += ws;
-        before += w < (int)wave ? ws : 0u;
-    }
+    uint32_t before = 0;
+    for (int w = 0; w < (int)wave; ++w) before += s_wsum[w];
     if (t < a.ntiles) a.tile_local[t] = before + incl - bits;
-    // the block's total as the tail of one segment (block 0 starts the stream),
-    // so that k_blk_scan turns the tails into block carries
-    if (tid == 0) a.blk_tail[blockIdx.x] = total | (blockIdx.x == 0 ? (kTailStarts | kTailHead) : 0ull);
+    if (tid == 0) {
+        unsigned long long c = 0;
+        for (int w = 0; w < kScanTiles / 64; ++w) c += s_wcar[w];
+        a.blk_carry[blockIdx.x] = c;
+    }
 }
 
 // Batch: the same scan restarted at every file.  One workgroup per block of
