@@ -30,10 +30,12 @@ WORKLOADS = {
     "markov_2GiB": ("2 GiB order-2 Markov text, 1 MiB chunks", 1 << 20, 256),
     "zipf256_2GiB": ("2 GiB i.i.d. Zipf(0.8) over 256 byte values, 1 MiB chunks", 1 << 20, 256),
 }
-# kernel ids of huff_ctx_kernel_time -> kernel names (decode: the staged kernel
-# for sub-blocks of 32..256 bytes, the direct one otherwise)
+# kernel ids of huff_ctx_kernel_time -> kernel names.  "scan" times the tile
+# bit counts and the offset scan together; "decode" times both staged launches
+# (table-only codes, longer codes) for sub-blocks of 32..256 bytes, the direct
+# kernel otherwise.
 KERNEL_NAMES = {"hist": "k_hist", "codebook": "k_codebook", "scan": "k_tile_scan", "encode": "k_encode",
-                "decode": "k_decode_staged"}
+                "decode": "k_decode_lds"}
 
 
 def kernel_source_hash() -> str:

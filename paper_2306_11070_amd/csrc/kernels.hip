@@ -1161,7 +1161,8 @@ struct DecTables {
 };
 
 __device__ __forceinline__ void load_tables(DecTables& t, const huff_dcb* cb, uint32_t lutBits) {
-    for (uint32_t i = threadIdx.x; i < (1u << lutBits); i += blockDim.x) t.lut[i] = cb->lut[i];
+    const uint32_t nl = 1u << min(lutBits, (uint32_t)HUFF_LUT_BITS);
+    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) t.lut[i] = cb->lut[i];
     for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
         t.first[i] = cb->first_code[i];
         t.cnt[i] = cb->count[i];
@@ -1288,8 +1289,10 @@ __device__ __forceinline__ uint4 dec16(Rd& r, const DecTables& t, uint32_t lutBi
                                        uint32_t& emin) {
     uint32_t o[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
+    for (int i = 0; i < 16; ++i) {
         o[i >> 2] |= dec1<kFits>(r, t, lutBits, maxLen, bad, used, emin) << (8 * (i & 3));
+        asm volatile("" : "+v"(o[i >> 2]), "+v"(emin));  // pack now: keeps table entries from staying live
+    }
     return make_uint4(o[0], o[1], o[2], o[3]);
 }
 
@@ -1419,14 +1422,124 @@ __global__ __launch_bounds__(256) void k_decode(DecArgs a) {
     if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
 }
 
-// Staged decoder for sub-blocks of S bytes (S = 32..256).  Each wave takes 64
-// consecutive sub-blocks: their stream bits are contiguous, so the wave loads
-// them once into LDS with coalesced 16-byte loads, then every lane decodes its
-// sub-block from LDS and stores every 16 decoded bytes with one 16-byte store.  A wave whose bits exceed the buffer (more than 8 bits per
-// byte on average) reads memory directly instead.
-template <int S, bool kBatch>
-__global__ __launch_bounds__(256) void k_decode_staged(DecArgs a) {
+// Orders the LDS accesses of one wave: what its lanes wrote before is seen
+// by all of its lanes after.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// S symbols of one lane's sub-block into registers, 16 per uint4 in stream
+// order, for codes that all fit the peek table.  The 64 stream bits at the
+// position are re-read from LDS every K symbols, at positions fixed at
+// compile time, so the unrolled run has no branch: a window read at most 31
+// bits into a word holds at least 33 bits ahead, enough for K codes of at
+// most maxLen bits and the peek of the last when
+// (K - 1) * maxLen + lutBits <= 33.  Each byte is packed as soon as it is
+// decoded, so the table entries do not stay live.  pos: bit position in the
+// buffer, advanced past the S codes.
+template <int S, int K>
+__device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, uint32_t& pos, const DecTables& t,
+                                              uint32_t lutBits, uint4 (&o)[S / 16], uint32_t& emin) {
+    uint64_t win = 0;
+    uint32_t cons = 0;
+#pragma unroll
+    for (uint32_t g = 0; g < S / 16; ++g) {
+        uint32_t w[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (uint32_t i = 0; i < 16; ++i) {
+            if ((g * 16 + i) % K == 0) {
+                pos += cons;
+                const uint32_t wi = min(pos >> 5, last - 1);
+                win = (((uint64_t)s[wi] << 32) | s[wi + 1]) << (pos & 31);
+                cons = 0;
+            }
+            const uint32_t e = t.lut[(uint32_t)(win >> 32) >> (32 - lutBits)];
+            emin = min(emin, e);
+            const uint32_t len = e >> 8;
+            win <<= len;
+            cons += len;
+            w[i >> 2] |= (e & 0xffu) << (8 * (i & 3));
+            asm volatile("" : "+v"(w[i >> 2]), "+v"(emin));
+        }
+        o[g] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+    pos += cons;
+}
+
+// Stores a whole wave's decoded sub-blocks (lane l holds bytes [l*S, l*S+S)
+// of the wave's output) through the wave's LDS buffer, which the wave no
+// longer reads: afterwards every store instruction writes 1 KB of
+// contiguous output, so every output line is written whole at once.  A
+// lane's g-th 16 bytes sit in LDS slot lane * G + ((g + lane) mod G), which
+// spreads one instruction's lanes over the banks.
+template <int S>
+__device__ __forceinline__ void wave_store(const uint4 (&o)[S / 16], uint32_t* buf, uint8_t* wave_out, int lane) {
+    constexpr uint32_t G = S / 16;
+    wave_lds_sync();
+    uint4* l4 = reinterpret_cast<uint4*>(buf);
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g) l4[lane * G + ((g + lane) & (G - 1))] = o[g];
+    wave_lds_sync();
+    uint4* g4 = reinterpret_cast<uint4*>(wave_out);
+#pragma unroll
+    for (uint32_t i = 0; i < G; ++i) {
+        const uint32_t e = i * 64 + lane, lp = e / G, g = e & (G - 1);
+        g4[e] = l4[lp * G + ((g + lp) & (G - 1))];
+    }
+}
+
+// 64-bit lane value of lane l (l uniform).
+__device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, uint32_t l) {
+    return ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(v >> 32), l) << 32) |
+           (uint32_t)__builtin_amdgcn_readlane((uint32_t)v, l);
+}
+
+// Copies stream words [base, base + 4 * nv) into a wave's LDS buffer with
+// 16-byte loads; words past the stream read as zero.
+__device__ __forceinline__ void stage_words(const FileDesc& f, uint64_t base, uint32_t nv, uint32_t* buf, int lane) {
+    const uint4* src = reinterpret_cast<const uint4*>(f.words) + (base >> 2);
+    uint4* dst = reinterpret_cast<uint4*>(buf);
+    for (uint32_t v = lane; v < nv; v += 64) {
+        const uint64_t wi = base + 4ull * v;
+        uint4 q;
+        if (wi + 4 <= f.nwords) {
+            q = src[v];
+        } else {
+            q.x = wi < f.nwords ? f.words[wi] : 0u;
+            q.y = wi + 1 < f.nwords ? f.words[wi + 1] : 0u;
+            q.z = wi + 2 < f.nwords ? f.words[wi + 2] : 0u;
+            q.w = wi + 3 < f.nwords ? f.words[wi + 3] : 0u;
+        }
+        dst[v] = q;
+    }
+}
+
+// Which codebooks a staged decode launch takes: those whose codes all fit
+// the peek table, or the others.  The two are separate kernels so that the
+// registers of the longer-code path do not limit the occupancy of the
+// table-only path; every block of a launch that its codebook does not
+// belong to exits at once.
+enum : int { kDecFits = 0, kDecLong = 1 };
+
+// Staged decoder for sub-blocks of S bytes (S = 32..256).  Each wave takes
+// 64 consecutive sub-blocks, one per lane: their stream bits are contiguous,
+// so the wave copies them once into its LDS buffer (sized for 8 bits per
+// byte) with 16-byte loads, and every lane decodes its sub-block from LDS.
+// A wave whose bits do not fit is staged in parts (halves, quarters, ... of
+// its lanes, one part after another).
+// Table-only codes: every whole sub-block is decoded into registers and the
+// wave stores them at the end, through LDS when all 64 are whole; the short
+// last sub-block of a stream is decoded byte by byte.  Longer codes: each
+// lane decodes with a refilled window and stores 64 bytes at a time; codes
+// longer than 32 bits are decoded straight from memory.
+template <int S, bool kBatch, int kMode>
+__global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
     constexpr uint32_t kInWords = 64 * S / 4 + 8;
+    constexpr uint32_t G = S / 16;
+    constexpr bool kFits = kMode == kDecFits;
+    constexpr int kLine = S < kDecLine ? S : kDecLine;
     __shared__ uint32_t s_in[4][kInWords];
     __shared__ DecTables t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1435,6 +1548,11 @@ __global__ __launch_bounds__(256) void k_decode_staged(DecArgs a) {
     else f = a.one;
     const huff_dcb* cb = f.cb;
     const uint32_t lutBits = cb->lut_bits, maxLen = cb->max_len;
+    if ((maxLen <= lutBits) != kFits) return;  // the other launch decodes this block
+    if (maxLen == 0 || maxLen > HUFF_MAX_CODE_LEN || lutBits == 0 || lutBits > HUFF_LUT_BITS) {
+        if (tid == 0) report(f.status, a.err, HUFF_E_CORRUPT);
+        return;
+    }
     load_tables(t, cb, lutBits);
 
     const uint64_t n = f.n;
@@ -1444,85 +1562,130 @@ __global__ __launch_bounds__(256) void k_decode_staged(DecArgs a) {
     const bool active = j < nitems;
     uint64_t start = 0, end = 0;
     if (active) item_bits(f, a, j, nitems, start, end);
-    // the wave's stream range, from its first and last active lanes
-    bool staged = false;
+    const uint32_t nsym = active ? (uint32_t)min<uint64_t>(S, n - j * S) : 0;
+    bool bad = start > end || end > f.nwords * 32ull;
+    const bool direct = !kFits && maxLen > 32;  // codes past the readers' 32-bit window
+
+    // parts: the smallest power of two P such that every run of 64 / P lanes fits the buffer
+    const bool wave_on = j0 < nitems;
+    const uint32_t la = wave_on ? (uint32_t)min<uint64_t>(63, nitems - 1 - j0) : 0;  // last active lane
+    uint32_t P = 1;
+    if (wave_on && !direct) {
+        for (;;) {
+            bool ok = true;
+            for (uint32_t l0 = 0; l0 <= la && ok; l0 += 64 / P) {
+                const uint64_t ws = read_lane_u64(start, l0), we = read_lane_u64(end, min(l0 + 64 / P - 1, la));
+                ok = we < ws || ((we + 31) >> 5) - ((ws >> 5) & ~3ull) + 4 <= kInWords;
+            }
+            if (ok || P == 64) break;
+            P *= 2;
+        }
+    }
+
+    // the first part (the whole wave when P = 1) is staged before the barrier
+    // that also publishes the tables
+    const uint32_t l1 = min(64 / P - 1, la);
     uint64_t base = 0;
-    if (j0 < nitems) {
-        const uint32_t la = (uint32_t)min<uint64_t>(63, nitems - 1 - j0);
-        const uint64_t ws = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(start >> 32), 0) << 32) |
-                            (uint32_t)__builtin_amdgcn_readlane((uint32_t)start, 0);
-        const uint64_t we = ((uint64_t)__builtin_amdgcn_readlane((uint32_t)(end >> 32), la) << 32) |
-                            (uint32_t)__builtin_amdgcn_readlane((uint32_t)end, la);
+    if (wave_on && !direct) {
+        const uint64_t ws = read_lane_u64(start, 0), we = read_lane_u64(end, l1);
         base = (ws >> 5) & ~3ull;
-        const uint64_t cnt = ((we + 31) >> 5) - base;
-        staged = we >= ws && cnt + 4 <= kInWords && maxLen <= 32;
-        if (staged) {
-            const uint32_t nv = (uint32_t)((cnt + 3) >> 2);
-            const uint4* src = reinterpret_cast<const uint4*>(f.words) + (base >> 2);
-            uint4* dst = reinterpret_cast<uint4*>(s_in[wave]);
-            for (uint32_t v = lane; v < nv; v += 64) {
-                const uint64_t wi = base + 4ull * v;
-                uint4 q;
-                if (wi + 4 <= f.nwords) {
-                    q = src[v];
+        const uint64_t cnt = we >= ws ? ((we + 31) >> 5) - base : 0;
+        stage_words(f, base, (uint32_t)min<uint64_t>((cnt + 3) >> 2, kInWords / 4), s_in[wave], lane);
+    }
+    __syncthreads();
+
+    uint32_t used = 0;
+    if (P == 1) {
+        if (active && !direct) {
+            const uint32_t bit0 = (uint32_t)(start - (base << 5));
+            if constexpr (kFits) {
+                const uint32_t k = (33u - lutBits) / maxLen + 1;  // symbols a re-read window covers
+                uint32_t emin = 0xffffffffu;
+                if (nsym == S) {
+                    uint4 o[G];
+                    uint32_t pos = bit0;
+                    if (k >= 8) dec_lane_fits<S, 8>(s_in[wave], kInWords - 1, pos, t, lutBits, o, emin);
+                    else if (k >= 4) dec_lane_fits<S, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, o, emin);
+                    else dec_lane_fits<S, 3>(s_in[wave], kInWords - 1, pos, t, lutBits, o, emin);
+                    used = pos - bit0;
+                    if ((j0 + 64) * S <= n) {
+                        wave_store<S>(o, s_in[wave], f.out + j0 * S, lane);
+                    } else {
+                        uint4* o4 = reinterpret_cast<uint4*>(f.out + j * S);
+#pragma unroll
+                        for (uint32_t g = 0; g < G; ++g) o4[g] = o[g];
+                    }
                 } else {
-                    q.x = wi < f.nwords ? f.words[wi] : 0u;
-                    q.y = wi + 1 < f.nwords ? f.words[wi + 1] : 0u;
-                    q.z = wi + 2 < f.nwords ? f.words[wi + 2] : 0u;
-                    q.w = wi + 3 < f.nwords ? f.words[wi + 3] : 0u;
+                    WinReader rd;
+                    rd.init(s_in[wave], kInWords, bit0, k);
+                    uint8_t* out = f.out + j * S;
+                    for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)rd.next(t, lutBits, emin);
+                    used = rd.pos + rd.cons - bit0;
                 }
-                dst[v] = q;
+                if (emin < 256u) bad = true;
+            } else {
+                LdsReader rd;
+                rd.init(s_in[wave], kInWords, bit0);
+                dec_run_k<kLine, false>(rd, t, lutBits, maxLen, bad, used, f.out + j * S, nsym);
+            }
+        }
+    } else {
+        // parts of 64 / P lanes, one after another, each lane storing its own bytes
+        for (uint32_t p = 0; p < P; ++p) {
+            const uint32_t q0 = p * (64 / P), q1 = min(q0 + 64 / P - 1, la);
+            if (q0 > la) break;
+            if (p > 0) {
+                wave_lds_sync();  // the previous part's lanes are done with the buffer
+                const uint64_t ws = read_lane_u64(start, q0), we = read_lane_u64(end, q1);
+                base = (ws >> 5) & ~3ull;
+                const uint64_t cnt = we >= ws ? ((we + 31) >> 5) - base : 0;
+                stage_words(f, base, (uint32_t)min<uint64_t>((cnt + 3) >> 2, kInWords / 4), s_in[wave], lane);
+                wave_lds_sync();
+            }
+            if (!active || lane < (int)q0 || lane > (int)q1) continue;
+            const uint32_t bit0 = (uint32_t)(start - (base << 5));
+            uint8_t* out = f.out + j * S;
+            uint32_t emin = 0xffffffffu;
+            if constexpr (kFits) {
+                WinReader rd;
+                rd.init(s_in[wave], kInWords, bit0, (33u - lutBits) / maxLen + 1);
+                for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)rd.next(t, lutBits, emin);
+                if (emin < 256u) bad = true;
+                used = rd.pos + rd.cons - bit0;
+            } else {
+                LdsReader rd;
+                rd.init(s_in[wave], kInWords, bit0);
+                for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)dec1<false>(rd, t, lutBits, maxLen, bad, used, emin);
             }
         }
     }
-    __syncthreads();
     if (!active) return;
-
-    const uint64_t first = j * S;
-    const uint32_t nsym = (uint32_t)min<uint64_t>(S, n - first);
-    uint8_t* out = f.out + first;
-    bool bad = start > end || end > f.nwords * 32ull || maxLen == 0 || maxLen > HUFF_MAX_CODE_LEN;
-    if (bad) {
-        report(f.status, a.err, HUFF_E_CORRUPT);
-        return;
-    }
-    if (maxLen > 32) {
-        uint64_t used = 0;
-        decode_generic(f, t, maxLen, start, nsym, out, bad, used);
-        if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
-        return;
-    }
-    uint32_t used = 0;
-    constexpr int kLine = S < kDecLine ? S : kDecLine;
-    if (staged) {
-        const uint32_t bit0 = (uint32_t)(start - (base << 5));
-        if (maxLen <= lutBits) {
-            WinReader rd;
-            rd.init(s_in[wave], kInWords, bit0, (33u - lutBits) / maxLen + 1);
-            dec_run_k<kLine, true>(rd, t, lutBits, maxLen, bad, used, out, nsym);
-            used = rd.pos + rd.cons - bit0;
-        } else {
-            LdsReader rd;
-            rd.init(s_in[wave], kInWords, bit0);
-            dec_run_k<kLine, false>(rd, t, lutBits, maxLen, bad, used, out, nsym);
+    if (direct) {
+        if (!bad) {
+            uint64_t u = 0;
+            decode_generic(f, t, maxLen, start, nsym, f.out + j * S, bad, u);
+            if (start + u != end) bad = true;
         }
-    } else {
-        BitReader rd;
-        rd.init(f.words, f.nwords, start);
-        dec_run<kLine>(rd, t, lutBits, maxLen, bad, used, out, nsym);
+    } else if (start + used != end) {
+        bad = true;
     }
-    if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
+    if (bad) report(f.status, a.err, HUFF_E_CORRUPT);
 }
 
 hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hipStream_t s) {
     const uint32_t sub = 1u << a.item_log2;
     if (a.use_sub && sub >= 32 && sub <= 256 && out_aligned) {
         const uint64_t blocks = (a.nitems + 255) / 256;
-#define HUFF_STAGED(SZ)                                                                                      \
-    if (sub == SZ) {                                                                                         \
-        if (a.files) hipLaunchKernelGGL((k_decode_staged<SZ, true>), dim3((uint32_t)blocks), dim3(256), 0, s, a); \
-        else hipLaunchKernelGGL((k_decode_staged<SZ, false>), dim3((uint32_t)blocks), dim3(256), 0, s, a);      \
-        return hipGetLastError();                                                                            \
+#define HUFF_STAGED(SZ)                                                                                        \
+    if (sub == SZ) {                                                                                           \
+        if (a.files) {                                                                                         \
+            hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecFits>), dim3((uint32_t)blocks), dim3(256), 0, s, a);  \
+            hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecLong>), dim3((uint32_t)blocks), dim3(256), 0, s, a);  \
+        } else {                                                                                               \
+            hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecFits>), dim3((uint32_t)blocks), dim3(256), 0, s, a); \
+            hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecLong>), dim3((uint32_t)blocks), dim3(256), 0, s, a); \
+        }                                                                                                      \
+        return hipGetLastError();                                                                              \
     }
         HUFF_STAGED(32)
         HUFF_STAGED(64)
