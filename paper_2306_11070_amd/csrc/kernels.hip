@@ -49,6 +49,14 @@ __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// Orders the LDS accesses of one wave: what its lanes wrote before is seen
+// by all of its lanes after.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) {
@@ -273,31 +281,47 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
                 if (f.sub_lo) f.sub_lo[0] = 0;
             }
         } else if (a.acc) {
-            for (int c = 0; c < kHistCopies; ++c) {
-                h += a.acc->acc[c][v];
-                a.acc->acc[c][v] = 0;
-            }
+            // all copies in flight at once, then summed, then cleared
+            unsigned long long part[kHistCopies];
+#pragma unroll
+            for (int c = 0; c < kHistCopies; ++c) part[c] = a.acc->acc[c][v];
+#pragma unroll
+            for (int c = 0; c < kHistCopies; ++c) h += part[c];
+#pragma unroll
+            for (int c = 0; c < kHistCopies; ++c) a.acc->acc[c][v] = 0;
             if (a.hist_out) a.hist_out[v] = h;
         } else {
             h = a.hist[v];
         }
         if (__syncthreads_or(h >> 56)) status = HUFF_E_INVAL;  // counts must fit the sort key
-        // leaves in (count, value) order: a present byte's rank is the number
-        // of smaller keys (absent bytes are key 0, below every present one;
-        // present keys are distinct), counted against all 256 keys in LDS
-        const uint64_t key = h && status == HUFF_OK ? (h << 8) | v : 0ull;
-        s_tmp[v] = key;
-        const uint32_t K = (uint32_t)__syncthreads_count(key != 0);
-        if (key) {
+        // leaves in (count, value) order: the present keys are gathered into
+        // LDS (keys are distinct), and a present byte's rank is the number of
+        // smaller keys among them
+        const uint32_t lane = v & 63, wave = v >> 6;
+        const bool present = h && status == HUFF_OK;
+        const uint64_t key = present ? (h << 8) | v : 0ull;
+        {
+            const uint64_t bal = __ballot(present);
+            if (lane == 0) s_rc[wave][0] = (uint32_t)__popcll(bal);
+            __syncthreads();
+            uint32_t off = 0;
+            for (uint32_t w = 0; w < wave; ++w) off += s_rc[w][0];
+            if (present) s_tmp[off + (uint32_t)__popcll(bal & ((1ull << lane) - 1))] = key;
+        }
+        const uint32_t K = s_rc[0][0] + s_rc[1][0] + s_rc[2][0] + s_rc[3][0];
+        __syncthreads();
+        if (present) {
             uint32_t r0 = 0, r1 = 0;
             const ulonglong2* k2 = reinterpret_cast<const ulonglong2*>(s_tmp);
-#pragma unroll 8
-            for (int u = 0; u < 128; ++u) {
+            uint32_t u = 0;
+#pragma unroll 4
+            for (; u < K / 2; ++u) {
                 const ulonglong2 p = k2[u];
                 r0 += p.x < key ? 1u : 0u;
                 r1 += p.y < key ? 1u : 0u;
             }
-            const uint32_t i = r0 + r1 - (256 - K);
+            if (K & 1) r0 += s_tmp[K - 1] < key ? 1u : 0u;
+            const uint32_t i = r0 + r1;
             s_w[i] = h;
             s_sym[i] = (uint8_t)v;
         }
@@ -307,7 +331,6 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
         } else if (K == 1) {
             myLen = h ? 1u : 0u;
         } else if (K >= 2) {
-            const uint32_t lane = v & 63, wave = v >> 6;
             uint32_t li = 0, qi = 0, m = 0;  // leaf head, internal head, internal nodes made
             uint32_t rounds = 0;
             while (m < K - 1) {
@@ -1420,14 +1443,6 @@ __global__ __launch_bounds__(256) void k_decode(DecArgs a) {
         decode_generic(f, t, maxLen, start, nsym, out, bad, used);
     }
     if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
-}
-
-// Orders the LDS accesses of one wave: what its lanes wrote before is seen
-// by all of its lanes after.
-__device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // S symbols of one lane's sub-block into registers, 16 per uint4 in stream
