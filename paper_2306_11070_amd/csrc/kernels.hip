@@ -165,6 +165,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
         y1 = load16(sr.in, sr.base + kEncTile / 2 + off, sr.n, al);
     };
     unsigned long long total = 0;
+    uint32_t run = 0;  // with tile_hist: the replicas' sum for byte value tid after the previous tile
     const uint64_t off = (uint64_t)tid * 16;
     uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
     Src cur = {nullptr, 0, 0};
@@ -183,16 +184,16 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
         count16(c0, sr.base + off, sr.n);
         count16(c1, sr.base + kEncTile / 2 + off, sr.n);
         if (a.tile_hist) {
+            // the replicas keep counting across tiles: a tile's count is the
+            // growth of their sum since the previous tile
             lds_barrier();
             if (tid < 256) {
-                uint32_t s = 0;
-                for (uint32_t r = 0; r < depth; ++r) {
-                    const uint32_t k = (tid << dl) | ((r + tid) & (depth - 1));
-                    s += sh[k];
-                    sh[k] = 0;
-                }
-                a.tile_hist[t * 256 + tid] = (uint16_t)s;
-                total += s;
+                uint32_t s = 0;  // modulo 2^32: the growth over one tile is exact
+                for (uint32_t r = 0; r < depth; ++r) s += sh[(tid << dl) | ((r + tid) & (depth - 1))];
+                const uint32_t c = s - run;
+                a.tile_hist[t * 256 + tid] = (uint16_t)c;
+                run = s;
+                total += c;
             }
             lds_barrier();
         }
