@@ -1533,11 +1533,12 @@ __device__ __forceinline__ void stage_words(const FileDesc& f, uint64_t base, ui
 }
 
 // Which codebooks a staged decode launch takes: those whose codes all fit
-// the peek table, or the others.  The two are separate kernels so that the
-// registers of the longer-code path do not limit the occupancy of the
-// table-only path; every block of a launch that its codebook does not
-// belong to exits at once.
-enum : int { kDecFits = 0, kDecLong = 1 };
+// the peek table, the others, or both.  For sub-blocks of up to 64 bytes the
+// first two are separate kernels, so that the registers of the longer-code
+// path do not limit the occupancy of the table-only path (every block of a
+// launch that its codebook does not belong to exits at once); from 128 bytes
+// the LDS buffer limits occupancy first, and one kernel takes both.
+enum : int { kDecFits = 0, kDecLong = 1, kDecBoth = 2 };
 
 // Staged decoder for sub-blocks of S bytes (S = 32..256).  Each wave takes
 // 64 consecutive sub-blocks, one per lane: their stream bits are contiguous,
@@ -1554,7 +1555,6 @@ template <int S, bool kBatch, int kMode>
 __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
     constexpr uint32_t kInWords = 64 * S / 4 + 8;
     constexpr uint32_t G = S / 16;
-    constexpr bool kFits = kMode == kDecFits;
     constexpr int kLine = S < kDecLine ? S : kDecLine;
     __shared__ uint32_t s_in[4][kInWords];
     __shared__ DecTables t;
@@ -1564,7 +1564,8 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
     else f = a.one;
     const huff_dcb* cb = f.cb;
     const uint32_t lutBits = cb->lut_bits, maxLen = cb->max_len;
-    if ((maxLen <= lutBits) != kFits) return;  // the other launch decodes this block
+    const bool fits = maxLen <= lutBits;
+    if (kMode != kDecBoth && fits != (kMode == kDecFits)) return;  // the other launch decodes this block
     if (maxLen == 0 || maxLen > HUFF_MAX_CODE_LEN || lutBits == 0 || lutBits > HUFF_LUT_BITS) {
         if (tid == 0) report(f.status, a.err, HUFF_E_CORRUPT);
         return;
@@ -1580,7 +1581,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
     if (active) item_bits(f, a, j, nitems, start, end);
     const uint32_t nsym = active ? (uint32_t)min<uint64_t>(S, n - j * S) : 0;
     bool bad = start > end || end > f.nwords * 32ull;
-    const bool direct = !kFits && maxLen > 32;  // codes past the readers' 32-bit window
+    const bool direct = !fits && maxLen > 32;  // codes past the readers' 32-bit window
 
     // parts: the smallest power of two P such that every run of 64 / P lanes fits the buffer
     const bool wave_on = j0 < nitems;
@@ -1614,7 +1615,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
     if (P == 1) {
         if (active && !direct) {
             const uint32_t bit0 = (uint32_t)(start - (base << 5));
-            if constexpr (kFits) {
+            if (fits) {
                 const uint32_t k = (33u - lutBits) / maxLen + 1;  // symbols a re-read window covers
                 uint32_t emin = 0xffffffffu;
                 if (nsym == S) {
@@ -1662,7 +1663,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
             const uint32_t bit0 = (uint32_t)(start - (base << 5));
             uint8_t* out = f.out + j * S;
             uint32_t emin = 0xffffffffu;
-            if constexpr (kFits) {
+            if (fits) {
                 WinReader rd;
                 rd.init(s_in[wave], kInWords, bit0, (33u - lutBits) / maxLen + 1);
                 for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)rd.next(t, lutBits, emin);
@@ -1688,26 +1689,30 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
     if (bad) report(f.status, a.err, HUFF_E_CORRUPT);
 }
 
+// Staged decode launches for one sub-block size.
+template <int SZ>
+hipError_t launch_staged(const DecArgs& a, hipStream_t s) {
+    const dim3 grid((uint32_t)((a.nitems + 255) / 256)), block(256);
+    if constexpr (SZ >= 128) {
+        if (a.files) hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecBoth>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecBoth>), grid, block, 0, s, a);
+    } else if (a.files) {
+        hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecFits>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecLong>), grid, block, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecFits>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecLong>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hipStream_t s) {
     const uint32_t sub = 1u << a.item_log2;
-    if (a.use_sub && sub >= 32 && sub <= 256 && out_aligned) {
-        const uint64_t blocks = (a.nitems + 255) / 256;
-#define HUFF_STAGED(SZ)                                                                                        \
-    if (sub == SZ) {                                                                                           \
-        if (a.files) {                                                                                         \
-            hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecFits>), dim3((uint32_t)blocks), dim3(256), 0, s, a);  \
-            hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecLong>), dim3((uint32_t)blocks), dim3(256), 0, s, a);  \
-        } else {                                                                                               \
-            hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecFits>), dim3((uint32_t)blocks), dim3(256), 0, s, a); \
-            hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecLong>), dim3((uint32_t)blocks), dim3(256), 0, s, a); \
-        }                                                                                                      \
-        return hipGetLastError();                                                                              \
-    }
-        HUFF_STAGED(32)
-        HUFF_STAGED(64)
-        HUFF_STAGED(128)
-        HUFF_STAGED(256)
-#undef HUFF_STAGED
+    if (a.use_sub && out_aligned) {
+        if (sub == 32) return launch_staged<32>(a, s);
+        if (sub == 64) return launch_staged<64>(a, s);
+        if (sub == 128) return launch_staged<128>(a, s);
+        if (sub == 256) return launch_staged<256>(a, s);
     }
     const uint64_t blocks = (a.nitems + block - 1) / block;
     if (a.files) hipLaunchKernelGGL(k_decode<true>, dim3((uint32_t)blocks), dim3(block), 0, s, a);
