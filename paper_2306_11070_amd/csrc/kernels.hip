@@ -1177,8 +1177,12 @@ __device__ __forceinline__ uint64_t peek64(const uint32_t* w, uint64_t nwords, u
 }
 
 // Canonical tables of one codebook, staged in LDS by every decode workgroup.
+// The peek table is split into a length table and a byte table, so that a
+// lookup needs no address scaling or field extraction and the length, which
+// the next lookup waits for, comes straight from its own load.
 struct DecTables {
-    uint16_t lut[1 << HUFF_LUT_BITS];
+    uint8_t len8[1 << HUFF_LUT_BITS];  // peek -> code length; 0: no code of at most lutBits bits
+    uint8_t sym8[1 << HUFF_LUT_BITS];  // peek -> byte
     unsigned long long first[64];
     uint32_t cnt[64], fidx[64];
     uint8_t sorted[256];
@@ -1186,7 +1190,11 @@ struct DecTables {
 
 __device__ __forceinline__ void load_tables(DecTables& t, const huff_dcb* cb, uint32_t lutBits) {
     const uint32_t nl = 1u << min(lutBits, (uint32_t)HUFF_LUT_BITS);
-    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) t.lut[i] = cb->lut[i];
+    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
+        const uint32_t e = cb->lut[i];
+        t.len8[i] = (uint8_t)(e >> 8);
+        t.sym8[i] = (uint8_t)e;
+    }
     for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
         t.first[i] = cb->first_code[i];
         t.cnt[i] = cb->count[i];
@@ -1265,36 +1273,38 @@ struct WinReader {
             cons = 0;
             c = 0;
         }
-        const uint32_t e = t.lut[(uint32_t)(win >> 32) >> (32 - lutBits)];
-        emin = min(emin, e);
-        const uint32_t len = e >> 8;
+        const uint32_t idx = (uint32_t)(win >> 32) >> (32 - lutBits);
+        const uint32_t len = t.len8[idx];
+        emin = min(emin, len);
         win <<= len;
         cons += len;
         ++c;
-        return e & 0xffu;
+        return t.sym8[idx];
     }
 };
 
 // kFits: every code is at most lutBits long, so the table alone decodes; a
-// table entry of 0 (no code matches) is then kept in emin and reported by
-// the caller instead of being branched on per symbol.
+// table length of 0 (no code matches) is then kept in emin (the least length
+// seen) and reported by the caller instead of being branched on per symbol.
 template <bool kFits, class Rd, typename U>
 __device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
                                          U& used, uint32_t& emin) {
     r.refill();
     const uint32_t top = (uint32_t)(r.win >> 32);
-    uint32_t e = t.lut[top >> (32 - lutBits)];
+    const uint32_t idx = top >> (32 - lutBits);
+    uint32_t len = t.len8[idx], sym = t.sym8[idx];
     if constexpr (kFits) {
-        emin = min(emin, e);
-    } else if ((e >> 8) == 0) {
-        e = decode_long(t, top, lutBits, maxLen);
-        if (e == 0) { bad = true; e = 1u << 8; }
+        emin = min(emin, len);
+    } else if (len == 0) {
+        const uint32_t e = decode_long(t, top, lutBits, maxLen);
+        if (e == 0) bad = true;
+        len = e ? e >> 8 : 1u;
+        sym = e & 0xffu;
     }
-    const uint32_t len = e >> 8;
     r.win <<= len;
     r.avail -= len;
     used += len;
-    return e & 0xffu;
+    return sym;
 }
 
 // The windowed reader decodes from the table alone; bits used are counted by
@@ -1353,7 +1363,7 @@ __device__ __forceinline__ void dec_run_k(Rd& r, const DecTables& t, uint32_t lu
     for (uint32_t k = 0; k < kG; ++k)
         if (k + rest >= kG) o4[groups - kG + k] = q[k];
     for (uint32_t i = groups << 4; i < nsym; ++i) out[i] = (uint8_t)dec1<kFits>(r, t, lutBits, maxLen, bad, used, emin);
-    if (kFits && emin < 256u) bad = true;
+    if (kFits && emin == 0u) bad = true;
 }
 
 // Picks the table-only decoder when every code fits the table.
@@ -1471,13 +1481,13 @@ __device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, 
                 win = (((uint64_t)s[wi] << 32) | s[wi + 1]) << (pos & 31);
                 cons = 0;
             }
-            const uint32_t e = t.lut[(uint32_t)(win >> 32) >> (32 - lutBits)];
-            emin = min(emin, e);
-            const uint32_t len = e >> 8;
+            const uint32_t idx = (uint32_t)(win >> 32) >> (32 - lutBits);
+            const uint32_t len = t.len8[idx];
+            emin = min(emin, len);
             win <<= len;
             cons += len;
-            w[i >> 2] |= (e & 0xffu) << (8 * (i & 3));
-            asm volatile("" : "+v"(w[i >> 2]), "+v"(emin));
+            w[i >> 2] |= (uint32_t)t.sym8[idx] << (8 * (i & 3));
+            if ((i & 3) == 3) asm volatile("" : "+v"(w[i >> 2]), "+v"(emin));
         }
         o[g] = make_uint4(w[0], w[1], w[2], w[3]);
     }
@@ -1639,7 +1649,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
                     for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)rd.next(t, lutBits, emin);
                     used = rd.pos + rd.cons - bit0;
                 }
-                if (emin < 256u) bad = true;
+                if (emin == 0u) bad = true;
             } else {
                 LdsReader rd;
                 rd.init(s_in[wave], kInWords, bit0);
@@ -1667,7 +1677,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
                 WinReader rd;
                 rd.init(s_in[wave], kInWords, bit0, (33u - lutBits) / maxLen + 1);
                 for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)rd.next(t, lutBits, emin);
-                if (emin < 256u) bad = true;
+                if (emin == 0u) bad = true;
                 used = rd.pos + rd.cons - bit0;
             } else {
                 LdsReader rd;
