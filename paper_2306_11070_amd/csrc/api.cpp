@@ -17,7 +17,7 @@ namespace {
 
 huff_params defaults(int num_cus) {
     huff_params p;
-    p.enc_blocks_per_cu = 3;  // LDS allows three encode workgroups per CU
+    p.enc_blocks_per_cu = 4;  // LDS allows four encode workgroups per CU
     p.hist_blocks = (uint32_t)num_cus * 4;
     p.hist_depth = 16;
     p.dec_block = 256;

@@ -761,6 +761,11 @@ hipError_t launch_blk_scan(const unsigned long long* blk_tail, unsigned long lon
 // threads write the same word.
 constexpr int kSlotWords = kEncUnit * 16 / 32 + 1;  // 64 bytes x 16 bits, plus a zero word
 constexpr int kSlotStride = kEncThreads + 1;           // word k of thread t at [k*stride + t]: banks differ along k
+// With codes of at most 8 bits a thread's slot needs rows 0..16 (64 x 8 bits
+// and the zero word); rows kLinRow.. then hold a whole tile's output words
+// (at most 16 KiB x 8 bits / 32 + 1 = 4097 of them).
+constexpr int kLinRow = kEncUnit * 8 / 32 + 1;
+static_assert((kSlotWords - kLinRow) * kSlotStride >= kEncTile * 8 / 32 + 1, "tile words fit above the slots");
 constexpr int kEncWaves = kEncThreads / 64;
 
 __device__ __forceinline__ uint32_t byte64(const uint4& a, const uint4& b, const uint4& c, const uint4& d, int i) {
@@ -1028,7 +1033,36 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
             uint32_t* wp = f.words + w0;
             const uint32_t* slot = s_slot + tid;
             uint32_t prevw = prefix;
-            if (capOK) {
+            if (capOK && group == 4) {
+                // Codes of at most 8 bits fill only slot rows below kLinRow:
+                // the tile's words are put together in order in the rows
+                // above, then the whole workgroup stores them, 1 KB of
+                // contiguous words per store instruction (group and capOK are
+                // the same for every thread of the tile).
+                const uint64_t ws = S >> 5;  // the tile's first word
+                uint32_t* lin = s_slot + kLinRow * kSlotStride;
+                const uint32_t at = (uint32_t)(w0 - ws);
+                constexpr uint32_t kLinWords = (kSlotWords - kLinRow) * kSlotStride;
+                for (uint32_t k = 0; k < nw; ++k) {
+                    const uint32_t cur = slot[k * kSlotStride];
+                    if (at + k < kLinWords) lin[at + k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
+                    prevw = cur;
+                }
+                __syncthreads();
+                // the tile's words: those whose last bit lies in the tile, and
+                // the stream's final partial word after the last tile
+                const uint32_t nwt = (uint32_t)((tileEnd >> 5) - ws) + (tileLast && (tileEnd & 31) ? 1u : 0u);
+                const uint32_t head = min(nwt, ((uint32_t)(0u - (uint32_t)(uintptr_t)(f.words + ws)) & 15u) >> 2);
+                if ((uint32_t)tid < head) f.words[ws + tid] = lin[tid];
+                const uint32_t body = (nwt - head) >> 2;
+                uint4* g4 = reinterpret_cast<uint4*>(f.words + ws + head);
+                for (uint32_t u = tid; u < body; u += kEncThreads) {
+                    const uint32_t o = head + 4 * u;
+                    g4[u] = make_uint4(lin[o], lin[o + 1], lin[o + 2], lin[o + 3]);
+                }
+                const uint32_t t0 = head + 4 * body;
+                if ((uint32_t)tid < nwt - t0) f.words[ws + t0 + tid] = lin[t0 + tid];
+            } else if (capOK) {
                 // single words up to a 16-byte boundary, then 16-byte stores
                 uint32_t k = 0;
                 const uint32_t head = min(nw, ((uint32_t)(0u - (uint32_t)(uintptr_t)wp) & 15u) >> 2);
