@@ -1557,22 +1557,37 @@ __device__ __forceinline__ uint64_t read_lane_u64(uint64_t v, uint32_t l) {
 }
 
 // Copies stream words [base, base + 4 * nv) into a wave's LDS buffer with
-// 16-byte loads; words past the stream read as zero.
+// 16-byte loads (nv <= kMaxV); words past the stream read as zero.  A lane
+// issues its loads four at a time before it writes them to LDS, so the copy
+// costs one memory round trip per four loads, not one per load, and holds
+// only four of them in registers.
+template <uint32_t kMaxV>
 __device__ __forceinline__ void stage_words(const FileDesc& f, uint64_t base, uint32_t nv, uint32_t* buf, int lane) {
+    constexpr uint32_t kPer = (kMaxV + 63) / 64, kBatch = 4;
     const uint4* src = reinterpret_cast<const uint4*>(f.words) + (base >> 2);
     uint4* dst = reinterpret_cast<uint4*>(buf);
-    for (uint32_t v = lane; v < nv; v += 64) {
-        const uint64_t wi = base + 4ull * v;
-        uint4 q;
-        if (wi + 4 <= f.nwords) {
-            q = src[v];
-        } else {
-            q.x = wi < f.nwords ? f.words[wi] : 0u;
-            q.y = wi + 1 < f.nwords ? f.words[wi + 1] : 0u;
-            q.z = wi + 2 < f.nwords ? f.words[wi + 2] : 0u;
-            q.w = wi + 3 < f.nwords ? f.words[wi + 3] : 0u;
+#pragma unroll
+    for (uint32_t r0 = 0; r0 < kPer; r0 += kBatch) {
+        uint4 q[kBatch];
+#pragma unroll
+        for (uint32_t r = 0; r < kBatch; ++r) {
+            const uint32_t v = lane + 64 * (r0 + r);
+            const uint64_t wi = base + 4ull * v;
+            q[r] = make_uint4(0, 0, 0, 0);
+            if (r0 + r < kPer && v < nv) {
+                if (wi + 4 <= f.nwords) {
+                    q[r] = src[v];
+                } else {
+                    q[r].x = wi < f.nwords ? f.words[wi] : 0u;
+                    q[r].y = wi + 1 < f.nwords ? f.words[wi + 1] : 0u;
+                    q[r].z = wi + 2 < f.nwords ? f.words[wi + 2] : 0u;
+                    q[r].w = wi + 3 < f.nwords ? f.words[wi + 3] : 0u;
+                }
+            }
         }
-        dst[v] = q;
+#pragma unroll
+        for (uint32_t r = 0; r < kBatch; ++r)
+            if (r0 + r < kPer && lane + 64 * (r0 + r) < nv) dst[lane + 64 * (r0 + r)] = q[r];
     }
 }
 
@@ -1651,7 +1666,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
         const uint64_t ws = read_lane_u64(start, 0), we = read_lane_u64(end, l1);
         base = (ws >> 5) & ~3ull;
         const uint64_t cnt = we >= ws ? ((we + 31) >> 5) - base : 0;
-        stage_words(f, base, (uint32_t)min<uint64_t>((cnt + 3) >> 2, kInWords / 4), s_in[wave], lane);
+        stage_words<kInWords / 4>(f, base, (uint32_t)min<uint64_t>((cnt + 3) >> 2, kInWords / 4), s_in[wave], lane);
     }
     __syncthreads();
 
@@ -1700,7 +1715,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
                 const uint64_t ws = read_lane_u64(start, q0), we = read_lane_u64(end, q1);
                 base = (ws >> 5) & ~3ull;
                 const uint64_t cnt = we >= ws ? ((we + 31) >> 5) - base : 0;
-                stage_words(f, base, (uint32_t)min<uint64_t>((cnt + 3) >> 2, kInWords / 4), s_in[wave], lane);
+                stage_words<kInWords / 4>(f, base, (uint32_t)min<uint64_t>((cnt + 3) >> 2, kInWords / 4), s_in[wave], lane);
                 wave_lds_sync();
             }
             if (!active || lane < (int)q0 || lane > (int)q1) continue;
