@@ -29,6 +29,10 @@ WORKLOADS = {
     "zipf96_1MiB": ("1 MiB i.i.d. Zipf(1.1) over 96 printable bytes, 64 KiB chunks", 64 << 10, 256),
     "markov_2GiB": ("2 GiB order-2 Markov text, 1 MiB chunks", 1 << 20, 256),
     "zipf256_2GiB": ("2 GiB i.i.d. Zipf(0.8) over 256 byte values, 1 MiB chunks", 1 << 20, 256),
+    "markov_1GiB": ("1 GiB order-2 Markov text (the leading 2^30 bytes of markov_2GiB), 1 MiB chunks, decode index "
+                    "every 128 bytes", 1 << 20, 128),
+    "zipf256_1GiB": ("1 GiB i.i.d. Zipf(0.8) over 256 byte values (the leading 2^30 bytes of zipf256_2GiB), 1 MiB "
+                     "chunks, decode index every 128 bytes", 1 << 20, 128),
 }
 # kernel ids of huff_ctx_kernel_time -> kernel names.  "scan" times the tile
 # bit counts and the offset scan together; "decode" times both staged launches

@@ -167,6 +167,8 @@ WORKLOADS = {
     "markov_45MiB": dict(n=45 << 20, chunk=256 << 10),
     "markov_2GiB": dict(n=1 << 31, chunk=None),
     "zipf256_2GiB": dict(n=1 << 31, chunk=None),
+    "markov_1GiB": dict(n=1 << 30, chunk=None),   # the leading 2^30 bytes of markov_2GiB
+    "zipf256_1GiB": dict(n=1 << 30, chunk=None),  # the leading 2^30 bytes of zipf256_2GiB
 }
 
 
@@ -178,8 +180,8 @@ def workload(name: str, n: int | None = None, out=None) -> np.ndarray:
         return zipf_iid(n, 1, 1.1, A96, out=out)
     if name == "markov_45MiB":
         return markov(n, 2, out=out)
-    if name == "markov_2GiB":
+    if name in ("markov_2GiB", "markov_1GiB"):
         return markov(n, 3, out=out)
-    if name == "zipf256_2GiB":
+    if name in ("zipf256_2GiB", "zipf256_1GiB"):
         return zipf_iid(n, 4, 0.8, A256, out=out)
     raise KeyError(name)

@@ -381,6 +381,50 @@ def _bits_of(words: np.ndarray, lo: int, hi: int) -> np.ndarray:
 # out-of-range offsets and a one-tile-ahead prefetch) ended in a GPU memory
 # fault.  That kernel has been taken out, but no cause was shown, so the case
 # stays off the GPU until one is.
+@pytest.mark.parametrize("name", ["markov_1GiB", "zipf256_1GiB"])
+def test_large_1GiB_properties_and_samples(codec, name):
+    """1 GiB streams (the leading half of the 2 GiB ones) in the launch
+    configuration the bench times (1 MiB chunks, 128-byte sub-blocks): exact
+    histogram, T = sum h*len, monotone index ending at T, sampled chunks and
+    sub-block offsets against the oracle, and an exact round trip."""
+    _say(f"{name}: generate")
+    n = 1 << 30
+    chunk, sub = 1 << 20, 128
+    a = datagen.workload(name)
+    assert a.size == n
+    x = dev(a)
+    st = codec.new_status()
+    _say(f"{name}: compress")
+    c = codec.compress(x, chunk, sub, status=st)
+    _check_status(st)
+    h = host_u64(c["hist"])
+    assert np.array_equal(h, np.bincount(a, minlength=256).astype(np.uint64))
+    ln = oracle.code_lengths(h)
+    code = oracle.canonical_codes(ln)
+    T = oracle.total_bits(h, ln)
+    off = host_u64(c["chunk_off"])
+    assert off[0] == 0 and off[-1] == T and np.all(np.diff(off.astype(np.int64)) >= 0)
+    words = host_u32(c["words"], (T + 31) // 32)
+    sub_lo = host_u32(c["sub_lo"])
+    rng = np.random.default_rng(1)
+    for ch in sorted(set(rng.integers(0, n // chunk, size=6).tolist()) | {0, n // chunk - 1}):
+        seg = a[ch * chunk:(ch + 1) * chunk]
+        w, o = oracle.encode(seg, ln, code, chunk)  # the chunk alone, with the stream's codebook
+        assert int(o[-1]) == int(off[ch + 1] - off[ch])
+        assert np.array_equal(_bits_of(words, int(off[ch]), int(off[ch + 1])), _bits_of(w, 0, int(o[-1])))
+        # the chunk's sub-block starts, shifted by the chunk's first bit
+        per = chunk // sub
+        _, fine = oracle.encode(seg, ln, code, sub)
+        want = (fine[:per].astype(np.uint64) + off[ch]) & np.uint64(0xFFFFFFFF)
+        assert np.array_equal(sub_lo[ch * per:(ch + 1) * per].astype(np.uint64), want), ch
+    _say(f"{name}: decode")
+    out = codec.decompress(c, status=st)
+    _check_status(st)
+    assert torch.equal(out, x)
+    del out, x, c
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.skip(reason="GPU memory fault in a run of this case; cause not yet shown, case kept off the GPU")
 @pytest.mark.parametrize("name", ["markov_2GiB", "zipf256_2GiB"])
 def test_full_size_2GiB_properties_and_samples(codec, name):
