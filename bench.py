@@ -138,6 +138,45 @@ def batch_leg(P, codec, nfiles: int, reps: int):
             "graph": True, "roundtrip_ok": bool(ok), "datagen_s": round(gen_s, 1)}
 
 
+SWEEP_CHUNKS = [16 << 10, 32 << 10, 64 << 10, 128 << 10, 256 << 10, 512 << 10, 1 << 20, 2 << 20, 4 << 20]
+
+
+def sweep_leg(P, codec, x, n: int, sub: int, reps: int):
+    """Compress and decode times over chunk sizes 16 KiB-4 MiB, with the
+    sub-block index and with the chunk index alone (decode parallelism is
+    then one lane per chunk); HIP events on the current stream, median of
+    `reps`.  The stream does not depend on the chunk size, only the index."""
+    import torch
+
+    def med(fn):
+        ts = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ts = sorted(ts[1:])
+        return ts[len(ts) // 2]
+
+    rows = []
+    out = torch.empty(n, dtype=torch.uint8, device=x.device)
+    for chunk in SWEEP_CHUNKS:
+        for s in (sub, 0):
+            st = codec.new_status()
+            c = codec.compress(x, chunk, s, status=st)
+            cms = med(lambda: codec.compress(x, chunk, s, status=st, out=c))
+            dms = med(lambda: codec.decompress(c, out=out, status=st))
+            torch.cuda.synchronize()
+            ok = int(st.item()) == 0 and bool(torch.equal(out, x))
+            rows.append({"chunk": chunk, "sub": s, "compress_ms": round(cms, 4), "decode_ms": round(dms, 4),
+                         "compress_GBps": round(n / (cms * 1e-3) / 1e9, 1),
+                         "decode_GBps": round(n / (dms * 1e-3) / 1e9, 1), "roundtrip_ok": ok})
+            del c
+    return rows
+
+
 def segments_leg(P, codec, x, T_global: int, seg: int, sub: int, reps: int):
     """The same input with a codebook per segment (one batch plan over the
     segments, graph replays), against the global codebook's size."""
@@ -283,6 +322,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-segments", action="store_true", help="skip the per-segment codebook leg")
     ap.add_argument("--segment", type=int, default=256 << 10, help="segment bytes of the per-segment codebook leg")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also time compress and decode over chunk sizes 16 KiB-4 MiB, with and without the sub-block index")
     ap.add_argument("--serve-seconds", type=float, default=2.0)
     ap.add_argument("--serve-pool", type=int, default=384)
     args = ap.parse_args()
@@ -431,6 +472,8 @@ def main():
                                 "sample": f"the whole {n}-byte workload, histogram+codebook+encode+decode, "
                                           f"{passes} passes averaged (plain serial C, one thread)"}
         line["bitexact_vs_oracle"] = bitexact
+    if args.sweep:
+        line["sweep"] = sweep_leg(P, codec, x, n, sub, 3)
     if not args.no_segments:
         line["segments"] = segments_leg(P, codec, x, T, args.segment, sub, 20)
     if not args.no_batch:
