@@ -360,6 +360,22 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
                     cI += s_rc[w][1];
                 }
                 const uint32_t pairs = (cL + cI) >> 1;
+                if (cL == 0 || cI == 0) {
+                    // one queue alone takes part: its nodes pair up in queue order
+                    const uint32_t base = cI == 0 ? li : K + qi;
+                    if (v < pairs) {
+                        const uint32_t x = base + 2 * v, y = x + 1, id = K + m + v;
+                        s_w[id] = s_w[x] + s_w[y];
+                        s_par[x] = (uint16_t)id;
+                        s_par[y] = (uint16_t)id;
+                    }
+                    __syncthreads();
+                    if (cI == 0) li += 2 * pairs;
+                    else qi += 2 * pairs;
+                    m += pairs;
+                    ++rounds;
+                    continue;
+                }
                 // merged position of each node taking part
                 // both binary searches in one loop, so that their LDS reads overlap:
                 // for the leaf, internal nodes strictly lighter; for the internal
