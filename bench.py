@@ -82,7 +82,7 @@ def cpu_baseline(a, chunk: int, passes: int):
     return r, out, dt
 
 
-def batch_leg(P, codec, nfiles: int, reps: int):
+def batch_leg(P, codec, nfiles: int, reps: int, sub: int = 128):
     """Many files, one codebook each: the batched path (one graph replay per
     operation) against a per-file loop of plain calls with a host sync per
     file, on the same files and buffers."""
@@ -96,7 +96,7 @@ def batch_leg(P, codec, nfiles: int, reps: int):
         data = list(ex.map(lambda i: datagen.batch_file(5, i), range(nfiles)))
     total = sum(a.size for a in data)
     xs = [torch.from_numpy(a).cuda() for a in data]
-    chunk, sub = 256 << 10, 256
+    chunk = 256 << 10
     files = P.batch_buffers(codec, xs, chunk, sub, bits_per_byte=8)  # byte codes average at most 8 bits
     gen_s = time.perf_counter() - t0
     b = P.Batch(codec, files, chunk, sub)
@@ -240,7 +240,7 @@ def serve_leg(P, seconds: float, pool_n: int, rates):
     sizes = [datagen.file_params(6, i, size_lo=1 << 10, size_hi=64 << 20)[0] for i in range(pool_n)]
     pool = [torch.from_numpy(datagen.markov(n, 6_000_000 + i)).cuda() for i, n in enumerate(sizes)]
     mean = float(np.mean(sizes))
-    srv = P.Server(mem_budget=64 << 30, nslots=2, max_batch=256, chunk_size=256 << 10, sub_size=256)
+    srv = P.Server(mem_budget=64 << 30, nslots=2, max_batch=256, chunk_size=256 << 10, sub_size=128)
     base = [srv.wait(srv.submit_compress(x)) for x in pool]
     ref = {i: srv.stream(r["handle"]) for i, r in enumerate(base)}
     rng = np.random.default_rng(6)
@@ -319,6 +319,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true", help="also run the plain copy kernel (counter calibration)")
     ap.add_argument("--no-batch", action="store_true", help="skip the many-file batch leg")
     ap.add_argument("--batch-files", type=int, default=4096)
+    ap.add_argument("--batch-sub", type=int, default=128, help="decode sub-block bytes of the batch leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--no-segments", action="store_true", help="skip the per-segment codebook leg")
     ap.add_argument("--segment", type=int, default=256 << 10, help="segment bytes of the per-segment codebook leg")
@@ -477,7 +478,7 @@ def main():
     if not args.no_segments:
         line["segments"] = segments_leg(P, codec, x, T, args.segment, sub, 20)
     if not args.no_batch:
-        line["batch"] = batch_leg(P, codec, args.batch_files, 10)
+        line["batch"] = batch_leg(P, codec, args.batch_files, 10, args.batch_sub)
     if not args.no_serve:
         line["serving"] = serve_leg(P, args.serve_seconds, args.serve_pool, (0.25, 0.5, 0.9, 1.2))
     print(json.dumps(line), flush=True)

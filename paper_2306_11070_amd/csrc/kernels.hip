@@ -1078,6 +1078,39 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
                 }
                 const uint32_t t0 = head + 4 * body;
                 if ((uint32_t)tid < nwt - t0) f.words[ws + t0 + tid] = lin[t0 + tid];
+            } else if (capOK && group == 3) {
+                // Codes of 9 or 10 bits: the slots fill the rows that the
+                // assembled tile would need, so each thread first takes its
+                // (at most kWords3) words into registers; after a barrier the
+                // whole slot region holds the tile's words in order, and the
+                // workgroup stores them as above.
+                constexpr uint32_t kWords3 = kEncUnit * 10 / 32 + 1;
+                const uint64_t ws = S >> 5;
+                const uint32_t at = (uint32_t)(w0 - ws);
+                uint32_t wv[kWords3];
+#pragma unroll
+                for (uint32_t k = 0; k < kWords3; ++k) {
+                    const uint32_t cur = k < nw ? slot[k * kSlotStride] : 0u;
+                    wv[k] = __builtin_amdgcn_alignbit(prevw, cur, sh);
+                    prevw = cur;
+                }
+                __syncthreads();  // every thread is done with its slot
+                constexpr uint32_t kAllWords = kSlotWords * kSlotStride;
+#pragma unroll
+                for (uint32_t k = 0; k < kWords3; ++k)
+                    if (k < nw && at + k < kAllWords) s_slot[at + k] = wv[k];
+                __syncthreads();
+                const uint32_t nwt = (uint32_t)((tileEnd >> 5) - ws) + (tileLast && (tileEnd & 31) ? 1u : 0u);
+                const uint32_t head = min(nwt, ((uint32_t)(0u - (uint32_t)(uintptr_t)(f.words + ws)) & 15u) >> 2);
+                if ((uint32_t)tid < head) f.words[ws + tid] = s_slot[tid];
+                const uint32_t body = (nwt - head) >> 2;
+                uint4* g4 = reinterpret_cast<uint4*>(f.words + ws + head);
+                for (uint32_t u = tid; u < body; u += kEncThreads) {
+                    const uint32_t o = head + 4 * u;
+                    g4[u] = make_uint4(s_slot[o], s_slot[o + 1], s_slot[o + 2], s_slot[o + 3]);
+                }
+                const uint32_t t0 = head + 4 * body;
+                if ((uint32_t)tid < nwt - t0) f.words[ws + t0 + tid] = s_slot[t0 + tid];
             } else if (capOK) {
                 // single words up to a 16-byte boundary, then 16-byte stores
                 uint32_t k = 0;
