@@ -141,7 +141,7 @@ enum {
     HUFF_K_CODEBOOK = 1,  /* k_codebook: lengths, canonical codes, decode tables */
     HUFF_K_SCAN = 2,      /* k_tile_bits + k_tile_scan: tile offsets */
     HUFF_K_ENCODE = 3,    /* k_encode: packing, segment and decode index */
-    HUFF_K_DECODE = 4,    /* k_decode_staged or k_decode */
+    HUFF_K_DECODE = 4,    /* k_decode_lds (all its launches) or k_decode */
     HUFF_K_COUNT = 5
 };
 huff_status huff_ctx_set_timing(huff_ctx* ctx, int enable);

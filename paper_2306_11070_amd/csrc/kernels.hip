@@ -1499,7 +1499,8 @@ __device__ __forceinline__ void item_bits(const FileDesc& f, const DecArgs& a, u
 }
 
 // Direct decoder: one lane per item, words read straight from memory.  Used
-// for chunk-only indexes and sub-blocks that the staged kernel does not take.
+// for chunk-only indexes and sub-blocks that the staged decoder (k_decode_lds)
+// does not take.
 template <bool kBatch>
 __global__ __launch_bounds__(256) void k_decode(DecArgs a) {
     __shared__ DecTables t;
@@ -1539,18 +1540,31 @@ __global__ __launch_bounds__(256) void k_decode(DecArgs a) {
     if (bad || start + used != end) report(f.status, a.err, HUFF_E_CORRUPT);
 }
 
+// Lengths of a complete canonical code that spans at most three lengths,
+// by comparison: the codes of length l, left-justified to 32 bits, fill one
+// range that ends where those of length l + 1 begin, so the length of the
+// code at the top of the window is `base` plus the number of the limits
+// (left-justified first codes of the longer lengths) that the top 32 bits
+// reach.  This keeps the table read off the chain from one code to the next.
+struct LenCmp {
+    uint32_t base, lim1, lim2;
+};
+
 // S symbols of one lane's sub-block into registers, 16 per uint4 in stream
 // order, for codes that all fit the peek table.  The 64 stream bits at the
 // position are re-read from LDS every K symbols, at positions fixed at
 // compile time, so the unrolled run has no branch: a window read at most 31
 // bits into a word holds at least 33 bits ahead, enough for K codes of at
 // most maxLen bits and the peek of the last when
-// (K - 1) * maxLen + lutBits <= 33.  Each byte is packed as soon as it is
-// decoded, so the table entries do not stay live.  pos: bit position in the
-// buffer, advanced past the S codes.
-template <int S, int K>
+// (K - 1) * maxLen + lutBits <= 33.  NC = 0: lengths from the length table
+// (a length of 0, no code, is kept in emin); NC = 1 or 2: lengths from NC
+// comparisons (LenCmp).  Each byte is packed as soon as it is decoded, so the
+// table entries do not stay live.  pos: bit position in the buffer, advanced
+// past the S codes.
+template <int S, int K, int NC>
 __device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, uint32_t& pos, const DecTables& t,
-                                              uint32_t lutBits, uint4 (&o)[S / 16], uint32_t& emin) {
+                                              uint32_t lutBits, const LenCmp lc, uint4 (&o)[S / 16],
+                                              uint32_t& emin) {
     uint64_t win = 0;
     uint32_t cons = 0;
 #pragma unroll
@@ -1564,9 +1578,16 @@ __device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, 
                 win = (((uint64_t)s[wi] << 32) | s[wi + 1]) << (pos & 31);
                 cons = 0;
             }
-            const uint32_t idx = (uint32_t)(win >> 32) >> (32 - lutBits);
-            const uint32_t len = t.len8[idx];
-            emin = min(emin, len);
+            const uint32_t top = (uint32_t)(win >> 32);
+            const uint32_t idx = top >> (32 - lutBits);
+            uint32_t len;
+            if constexpr (NC == 0) {
+                len = t.len8[idx];
+                emin = min(emin, len);
+            } else {
+                len = lc.base + (top >= lc.lim1 ? 1u : 0u);
+                if constexpr (NC == 2) len += top >= lc.lim2 ? 1u : 0u;
+            }
             win <<= len;
             cons += len;
             w[i >> 2] |= (uint32_t)t.sym8[idx] << (8 * (i & 3));
@@ -1729,9 +1750,34 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
                 if (nsym == S) {
                     uint4 o[G];
                     uint32_t pos = bit0;
-                    if (k >= 8) dec_lane_fits<S, 8>(s_in[wave], kInWords - 1, pos, t, lutBits, o, emin);
-                    else if (k >= 4) dec_lane_fits<S, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, o, emin);
-                    else dec_lane_fits<S, 3>(s_in[wave], kInWords - 1, pos, t, lutBits, o, emin);
+                    // a complete code of at most three lengths: lengths by comparison
+                    uint32_t minLen = maxLen;
+                    for (uint32_t l = maxLen; l >= 1; --l)
+                        if (t.cnt[l]) minLen = l;
+                    const uint32_t span = maxLen - minLen;
+                    const bool cmp = span <= 2 && k >= 4 && t.first[maxLen] + t.cnt[maxLen] == (1ull << maxLen);
+                    LenCmp lc = {0u, 0u, 0u};
+                    if (span == 0) {
+                        lc.base = minLen - 1;  // one length: the comparison with 0 always adds 1
+                    } else {
+                        lc.base = minLen;
+                        lc.lim1 = (uint32_t)(t.first[minLen + 1] << (32 - (minLen + 1)));
+                        if (span == 2) lc.lim2 = (uint32_t)(t.first[minLen + 2] << (32 - (minLen + 2)));
+                    }
+                    uint32_t* sb = s_in[wave];
+                    if (cmp && span == 2) {
+                        if (k >= 8) dec_lane_fits<S, 8, 2>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        else dec_lane_fits<S, 4, 2>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    } else if (cmp) {
+                        if (k >= 8) dec_lane_fits<S, 8, 1>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        else dec_lane_fits<S, 4, 1>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    } else if (k >= 8) {
+                        dec_lane_fits<S, 8, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    } else if (k >= 4) {
+                        dec_lane_fits<S, 4, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    } else {
+                        dec_lane_fits<S, 3, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    }
                     used = pos - bit0;
                     if ((j0 + 64) * S <= n) {
                         wave_store<S>(o, s_in[wave], f.out + j0 * S, lane);
