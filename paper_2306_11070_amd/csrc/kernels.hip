@@ -521,18 +521,28 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
         d->first_index[v] = s_fidx[v];
         d->count[v] = s_cnt[v];
     }
-    for (uint32_t p = v; p < (1u << HUFF_LUT_BITS); p += 256) {
-        uint16_t e = 0;
-        if (p < (1u << lutBits)) {
-            for (uint32_t l = 1; l <= lutBits; ++l) {
-                const uint64_t c = p >> (lutBits - l);
-                if (c - s_first[l] < s_cnt[l]) {
-                    e = (uint16_t)(s_sorted[s_fidx[l] + (uint32_t)(c - s_first[l])] | (l << 8));
-                    break;
-                }
-            }
+    // peek table: the codes of length l, left-justified to lutBits bits, fill
+    // [lo[l], lo[l] + cnt[l] << (lutBits - l)); the ranges are read once into
+    // registers and every entry finds its length by comparisons
+    {
+        uint32_t lo[HUFF_LUT_BITS + 1], span[HUFF_LUT_BITS + 1];
+#pragma unroll
+        for (uint32_t l = 1; l <= HUFF_LUT_BITS; ++l) {
+            const bool on = l <= lutBits && s_cnt[l] != 0;
+            lo[l] = on ? (uint32_t)(s_first[l] << (lutBits - l)) : 0u;
+            span[l] = on ? s_cnt[l] << (lutBits - l) : 0u;
         }
-        d->lut[p] = e;
+        for (uint32_t p = v; p < (1u << HUFF_LUT_BITS); p += 256) {
+            uint32_t len = 0;
+#pragma unroll
+            for (uint32_t l = 1; l <= HUFF_LUT_BITS; ++l) len = p - lo[l] < span[l] ? l : len;
+            uint16_t e = 0;
+            if (len) {
+                const uint32_t c = p >> (lutBits - len);
+                e = (uint16_t)(s_sorted[s_fidx[len] + (uint32_t)(c - s_first[len])] | (len << 8));
+            }
+            d->lut[p] = e;
+        }
     }
     if (v == 0) {
         d->nsym = K2;
