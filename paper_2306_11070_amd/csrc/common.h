@@ -23,7 +23,7 @@ constexpr uint64_t kMaxN = 1ull << 38;
 // w % kHistCopies, which spreads same-address atomics; the kernel that
 // consumes the counts (finalize or codebook) sums the copies and zeroes them
 // for the next launch.
-constexpr int kHistCopies = 32;
+constexpr int kHistCopies = 16;
 struct HistState {
     unsigned long long acc[kHistCopies][256];
 };
