@@ -124,8 +124,13 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
     __shared__ uint32_t sh[256 * kHistMaxDepth];
     const uint32_t dl = a.depth_log2, depth = 1u << dl;
     const uint32_t tid = threadIdx.x;
-    for (uint32_t i = tid; i < 256u * depth; i += kHistThreads) sh[i] = 0;
+    // with per-tile histograms and room for two replica sets, tiles count into
+    // the sets in turn: a set is read after its tile while the next tile
+    // counts into the other one, so a tile needs one barrier, not two
+    const bool dbl = a.tile_hist != nullptr && 2 * depth <= (uint32_t)kHistMaxDepth;
+    for (uint32_t i = tid; i < (dbl ? 512u : 256u) * depth; i += kHistThreads) sh[i] = 0;
     const uint32_t rep = tid & (depth - 1);
+    uint32_t* set = sh;
     const uint64_t ntiles = kBatch ? a.ntiles : (a.n + kEncTile - 1) / kEncTile;
     const uint64_t t0 = (uint64_t)blockIdx.x * a.tiles_per_block;
     const uint64_t t1 = min(ntiles, t0 + a.tiles_per_block);
@@ -142,7 +147,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
             return {a.in, a.n, t * (uint64_t)kEncTile};
         }
     };
-    auto count = [&](uint32_t b) { atomicAdd(&sh[(b << dl) | rep], 1u); };
+    auto count = [&](uint32_t b) { atomicAdd(&set[(b << dl) | rep], 1u); };
     auto count4 = [&](uint32_t w) {
         count(w & 0xffu);
         count((w >> 8) & 0xffu);
@@ -165,7 +170,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
         y1 = load16(sr.in, sr.base + kEncTile / 2 + off, sr.n, al);
     };
     unsigned long long total = 0;
-    uint32_t run = 0;  // with tile_hist: the replicas' sum for byte value tid after the previous tile
+    uint32_t run = 0, run2 = 0;  // with tile_hist: each set's sum for byte value tid after its previous tile
     const uint64_t off = (uint64_t)tid * 16;
     uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
     Src cur = {nullptr, 0, 0};
@@ -181,21 +186,27 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
             cur = src(t + 1);
             load2(cur, q0, q1);
         }
+        const bool odd = dbl && ((t - t0) & 1);
+        set = odd ? sh + 256 * depth : sh;
         count16(c0, sr.base + off, sr.n);
         count16(c1, sr.base + kEncTile / 2 + off, sr.n);
         if (a.tile_hist) {
             // the replicas keep counting across tiles: a tile's count is the
-            // growth of their sum since the previous tile
+            // growth of their set's sum since that set's previous tile
             lds_barrier();
             if (tid < 256) {
                 uint32_t s = 0;  // modulo 2^32: the growth over one tile is exact
-                for (uint32_t r = 0; r < depth; ++r) s += sh[(tid << dl) | ((r + tid) & (depth - 1))];
-                const uint32_t c = s - run;
+                for (uint32_t r = 0; r < depth; ++r) s += set[(tid << dl) | ((r + tid) & (depth - 1))];
+                const uint32_t c = s - (odd ? run2 : run);
                 a.tile_hist[t * 256 + tid] = (uint16_t)c;
-                run = s;
+                if (odd) run2 = s; else run = s;
                 total += c;
             }
-            lds_barrier();
+            // one set: no thread may count the next tile before every thread
+            // has read this one (two sets: the next tile counts into the other
+            // set, and the barrier after it orders this set's reads before the
+            // tile after that counts here again)
+            if (!dbl) lds_barrier();
         }
     }
     if constexpr (!kBatch) {
