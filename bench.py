@@ -330,8 +330,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this codec runs on a single MI355X; multi-GPU sharding is not built "
-              "(see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: this codec runs on a single MI355X and multi-GPU sharding is not "
+              "built. Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
