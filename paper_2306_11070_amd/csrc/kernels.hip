@@ -936,6 +936,11 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
     cur.before = cur.local = 0;
     cur.carry = 0;
     if ((uint64_t)blockIdx.x < a.ntiles) fetch(blockIdx.x, cur);
+    // the previous tile stored its words from the slot rows at and above
+    // kLinRow: every read of LDS it still makes comes after its barriers, and
+    // from those rows only, which the next tile (same codebook, codes of at
+    // most 8 bits) writes only after its scan barrier
+    bool prevLin = false;
     for (uint64_t g = blockIdx.x; g < a.ntiles; g += gridDim.x) {
         const FileDesc& f = fileOf(g);
         const uint64_t j = g - f.first;
@@ -949,7 +954,8 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
         // the next tile's loads: unconditional (the last tile re-reads itself)
         const uint64_t gn = g + gridDim.x;
         fetch(gn < a.ntiles ? gn : g, cur);
-        __syncthreads();  // the previous tile is done with the LDS slots and tables
+        if (!(prevLin && f.cb == loaded)) __syncthreads();  // the previous tile is done with the LDS slots and tables
+        prevLin = false;
         if (tid < 8) s_prev4[tid] = prev4;
         if (f.cb != loaded) {
             const uint32_t maxLen = f.cb->max_len;
@@ -1099,6 +1105,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
                 }
                 const uint32_t t0 = head + 4 * body;
                 if ((uint32_t)tid < nwt - t0) f.words[ws + t0 + tid] = lin[t0 + tid];
+                prevLin = true;
             } else if (capOK && group == 3) {
                 // Codes of 9 or 10 bits: the slots fill the rows that the
                 // assembled tile would need, so each thread first takes its
