@@ -290,6 +290,7 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
             sa.tile_bits = c->tile_bits;
             sa.ntiles = ntiles;
             sa.tile_local = c->tile_local;
+            sa.blk_tail = c->blk_tail;
             sa.blk_carry = c->blk_carry;
             st = hip_status(launch_tile_scan(sa, s));
         }
@@ -508,7 +509,8 @@ huff_status huff_copy(huff_ctx* c, const void* d_src, void* d_dst, uint64_t byte
     if (bytes == 0) return HUFF_OK;
     if (((uintptr_t)d_src & 15u) || ((uintptr_t)d_dst & 15u)) return HUFF_E_INVAL;
     DeviceGuard g(c->device);
-    return hip_status(launch_copy(d_src, d_dst, bytes, as_stream(stream)));
+    // persistent grid: eight 256-thread workgroups per compute unit fill it
+    return hip_status(launch_copy(d_src, d_dst, bytes, (uint32_t)c->num_cus * 8, as_stream(stream)));
 }
 
 }  // extern "C"
@@ -645,9 +647,8 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
     sa.ntiles = b->ntiles;
     sa.tile_local = b->d_tile_local;
     sa.blk_tail = b->d_blk_tail;
-    st = hip_status(launch_tile_scan(sa, s));
-    if (st != HUFF_OK) return st;
-    st = hip_status(launch_blk_scan(b->d_blk_tail, b->d_blk_carry, (b->ntiles + kScanTilesPerBlock - 1) / kScanTilesPerBlock, s));
+    sa.blk_carry = b->d_blk_carry;
+    st = hip_status(launch_tile_scan(sa, s));  // block scans, then the carries across blocks
     if (st != HUFF_OK) return st;
     EncArgs e;
     memset(&e, 0, sizeof(e));

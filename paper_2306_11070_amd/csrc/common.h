@@ -58,12 +58,13 @@ struct EncArgs {
     int32_t* err;           // fallback status word
 };
 
-// Tile offsets are a scan in two levels.  One stream: k_tile_scan scans the
-// tiles of each 1024-tile block and sums the bits of all earlier tiles into
-// the block's carry.  A batch: k_tile_scan_seg scans each block restarting at
-// every file, and k_blk_scan carries the open file's running total from
-// block to block; blk_tail packs, per block, the bits of its last segment
-// (low 62 bits) with two flags.
+// Tile offsets are a scan in two levels.  A short stream: k_tile_scan scans
+// the tiles of each 1024-tile block and sums the bits of all earlier tiles
+// into the block's carry.  A batch, or a longer stream (one segment):
+// k_tile_scan_seg scans each block restarting at every file, and k_blk_scan
+// carries the open file's running total from block to block; blk_tail packs,
+// per block, the bits of its last segment (low 62 bits) with two flags.
+// launch_tile_scan queues both levels.
 constexpr unsigned long long kTailStarts = 1ull << 63;  // the block's last segment starts inside the block
 constexpr unsigned long long kTailHead = 1ull << 62;    // a file starts at the block's first tile
 constexpr unsigned long long kTailBits = kTailHead - 1;
@@ -86,8 +87,8 @@ struct ScanArgs {
     const uint32_t* tile_file;  // ... and file index of every tile
     uint64_t ntiles;
     uint32_t* tile_local;
-    unsigned long long* blk_tail;   // batch: last segment of each block, with flags
-    unsigned long long* blk_carry;  // one stream: bits of all tiles before each block
+    unsigned long long* blk_tail;   // last segment of each block, with flags (segmented scan)
+    unsigned long long* blk_carry;  // out: bits of the open segment before each block
 };
 
 struct DecArgs {
@@ -139,7 +140,7 @@ hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo, hipStream_t s);
 // out_aligned: every output is 16-byte aligned (the staged decoder requires it)
 hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hipStream_t s);
-hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, uint32_t blocks, hipStream_t s);
 hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
 

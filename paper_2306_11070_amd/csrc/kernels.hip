@@ -649,10 +649,16 @@ hipError_t launch_tile_bits_hist(const TileBitsArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-// One stream: exclusive scan of the tile bits inside blocks of kScanTiles
-// tiles, one thread per tile, and each block's carry.  tile_local may be the
-// tile_bits buffer itself (each thread reads its tile's count before it
-// writes that tile's offset).
+// One stream of at most kInlineCarryBlocks scan blocks: exclusive scan of
+// the tile bits inside blocks of kScanTiles tiles, one thread per tile, and
+// each block's carry summed from the tile counts of all earlier blocks (at
+// most (kInlineCarryBlocks - 1) x kScanTiles reads per block, so one launch
+// does both levels).  tile_local must not alias tile_bits: a block reads the
+// counts of earlier blocks while those blocks write their offsets.  Longer
+// streams take the segmented scan below (a single segment) and k_blk_scan,
+// whose cost grows linearly with the tile count.
+constexpr uint64_t kInlineCarryBlocks = 8;
+
 __global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
     __shared__ uint32_t s_wsum[kScanTiles / 64];
     __shared__ unsigned long long s_wcar[kScanTiles / 64];
@@ -680,9 +686,11 @@ __global__ __launch_bounds__(kScanTiles) void k_tile_scan(ScanArgs a) {
     }
 }
 
-// Batch: the same scan restarted at every file.  One workgroup per block of
-// kScanTiles tiles, one thread per tile; tile_local may be the tile_bits
-// buffer itself.
+// Batch: the same scan restarted at every file (without a file table the
+// whole stream is one file).  One workgroup per block of kScanTiles tiles,
+// one thread per tile; tile_local may be the tile_bits buffer itself (each
+// thread reads only its own tile's count, before it writes that tile's
+// offset).
 __global__ __launch_bounds__(kScanTiles) void k_tile_scan_seg(ScanArgs a) {
     __shared__ uint32_t s_wsum[kScanTiles / 64];
     __shared__ uint32_t s_excl[kScanTiles];
@@ -694,7 +702,7 @@ __global__ __launch_bounds__(kScanTiles) void k_tile_scan_seg(ScanArgs a) {
     uint32_t bits = 0;
     uint64_t first = 0;  // first tile of the tile's file
     if (t < a.ntiles) {
-        first = a.files[a.tile_file[t]].first;
+        if (a.files) first = a.files[a.tile_file[t]].first;
         bits = a.tile_bits[t];
     }
     const uint32_t incl = wave_incl_scan(bits);
@@ -772,9 +780,15 @@ hipError_t launch_tile_bits(const uint8_t* in, uint64_t n, const huff_dcb* cb, u
 
 hipError_t launch_tile_scan(const ScanArgs& a, hipStream_t s) {
     const uint64_t blocks = (a.ntiles + kScanTiles - 1) / kScanTiles;
-    if (a.files) hipLaunchKernelGGL(k_tile_scan_seg, dim3((uint32_t)blocks), dim3(kScanTiles), 0, s, a);
-    else hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)blocks), dim3(kScanTiles), 0, s, a);
-    return hipGetLastError();
+    if (blocks == 0) return hipSuccess;
+    if (!a.files && blocks <= kInlineCarryBlocks) {
+        hipLaunchKernelGGL(k_tile_scan, dim3((uint32_t)blocks), dim3(kScanTiles), 0, s, a);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL(k_tile_scan_seg, dim3((uint32_t)blocks), dim3(kScanTiles), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_blk_scan(a.blk_tail, a.blk_carry, blocks, s);
 }
 
 hipError_t launch_blk_scan(const unsigned long long* blk_tail, unsigned long long* blk_carry, uint64_t nblk,
@@ -951,9 +965,9 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
         const uint4 x0 = cur.x0, x1 = cur.x1, x2 = cur.x2, x3 = cur.x3;
         const uint32_t prev4 = cur.before;
         const uint64_t S = cur.carry + cur.local;  // the tile's first stream bit
-        // the next tile's loads: unconditional (the last tile re-reads itself)
+        // the next tile's loads (none after the workgroup's last tile)
         const uint64_t gn = g + gridDim.x;
-        fetch(gn < a.ntiles ? gn : g, cur);
+        if (gn < a.ntiles) fetch(gn, cur);
         if (!(prevLin && f.cb == loaded)) __syncthreads();  // the previous tile is done with the LDS slots and tables
         prevLin = false;
         if (tid < 8) s_prev4[tid] = prev4;
@@ -1916,21 +1930,37 @@ hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t
     return hipGetLastError();
 }
 
+// The bandwidth probe: a persistent grid copies 16-byte vectors, each
+// thread keeping kCopyInFlight loads in flight before it stores them, with
+// non-temporal loads and stores (the probe's data is never reused).  The
+// bytes past the last whole vector are copied by the first workgroup.
+constexpr int kCopyInFlight = 8;
+typedef uint32_t v4u32_t __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void k_copy(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, uint64_t bytes) {
     const uint64_t nvec = bytes >> 4;
-    const uint4* s = reinterpret_cast<const uint4*>(src);
-    uint4* d = reinterpret_cast<uint4*>(dst);
+    const v4u32_t* s = reinterpret_cast<const v4u32_t*>(src);
+    v4u32_t* d = reinterpret_cast<v4u32_t*>(dst);
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nvec; i += stride) d[i] = s[i];
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + (kCopyInFlight - 1) * stride < nvec; i += kCopyInFlight * stride) {
+        v4u32_t v[kCopyInFlight];
+#pragma unroll
+        for (int k = 0; k < kCopyInFlight; ++k) v[k] = __builtin_nontemporal_load(s + i + k * stride);
+#pragma unroll
+        for (int k = 0; k < kCopyInFlight; ++k) __builtin_nontemporal_store(v[k], d + i + k * stride);
+    }
+    for (; i < nvec; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(s + i), d + i);
     if (blockIdx.x == 0)
-        for (uint64_t i = (nvec << 4) + threadIdx.x; i < bytes; i += blockDim.x) dst[i] = src[i];
+        for (uint64_t b = (nvec << 4) + threadIdx.x; b < bytes; b += blockDim.x) dst[b] = src[b];
 }
 
-hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s) {
-    uint64_t blocks = (bytes / 16 + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_copy, dim3((uint32_t)blocks), dim3(256), 0, s, (const uint8_t*)src, (uint8_t*)dst, bytes);
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, uint32_t blocks, hipStream_t s) {
+    const uint64_t need = (bytes / 16 + 255) / 256;
+    uint64_t g = blocks ? blocks : 2048;
+    if (g > need) g = need;
+    if (g == 0) g = 1;
+    hipLaunchKernelGGL(k_copy, dim3((uint32_t)g), dim3(256), 0, s, (const uint8_t*)src, (uint8_t*)dst, bytes);
     return hipGetLastError();
 }
 

@@ -220,3 +220,39 @@ def test_batch_decode_needs_outputs(P, codec):
         _check_file(f, a, 4096, 64)
     b.close()
 
+
+
+def test_batch_scan_carries_across_blocks(P, codec):
+    """Files that open and close across the 16 MiB scan blocks (1024 tiles of
+    16 KiB): a file that starts exactly at a block's first tile, files that
+    start inside a block and end in a later one, a file that covers a whole
+    block, and empty and tiny files between them.  Every file is compared
+    with the oracle on that file alone (histogram, words, chunk and
+    sub-block offsets), and decoded back."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    MiB = 1 << 20
+    # tile starts: 0, 1024 (block 1's first tile), 2304, 2305, 2305, 3074,
+    # 3074 (covers block 4), 5635, 5636; 6660 tiles in 7 blocks
+    sizes = [16 * MiB, 20 * MiB, 1, 0, 12 * MiB + 5, 0, 40 * MiB + 7, 3, 16 * MiB - 16384 + 1]
+    _say(f"batch across scan blocks: {len(sizes)} files, {sum(sizes)} bytes")
+    data = [_file_data(i, n) for i, n in enumerate(sizes)]
+    chunk, sub = 256 << 10, 128
+    xs = [dev(a) for a in data]
+    files = P.batch_buffers(codec, xs, chunk, sub)
+    b = P.Batch(codec, files, chunk, sub)
+    for rep in range(2):
+        for f in files:
+            f["words"].fill_(-1)
+            f["chunk_off"].fill_(-1)
+            f["sub_lo"].fill_(-1)
+            f["out"].fill_(0)
+        b.compress(graph=rep == 1)
+        b.decode(graph=rep == 1)
+        torch.cuda.synchronize()
+        with ThreadPoolExecutor(8) as ex:
+            refs = list(ex.map(lambda a: oracle.compress(a, chunk, sub=sub), data))
+        for i, (f, a, r) in enumerate(zip(files, data, refs)):
+            _check_file(f, a, chunk, sub, r)
+            assert torch.equal(f["out"], xs[i]), (rep, i)
+    b.close()

@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle,
 bit for bit, on seeded inputs.  Sizes span several tiles with ragged tails;
-the full-size workloads are checked on sampled chunks and on properties that
-hold at any size."""
+the 45 MiB and 1 GiB workloads are compared in full (every word, chunk offset
+and sub-block offset)."""
 import sys
 
 import numpy as np
@@ -9,6 +9,7 @@ import pytest
 
 import datagen
 import oracle
+from oracle import pieces as oracle_pieces
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -370,31 +371,13 @@ def test_small_zipf_1MiB(codec):
     _roundtrip(codec, a, 64 << 10, 0)
 
 
-def _bits_of(words: np.ndarray, lo: int, hi: int) -> np.ndarray:
-    """Stream bits [lo, hi) as a 0/1 array (MSB-first words)."""
-    w0, w1 = lo // 32, (hi + 31) // 32
-    b = np.unpackbits(words[w0:w1].astype(">u4").view(np.uint8))
-    return b[lo - 32 * w0: hi - 32 * w0]
-
-
-# A run of this test against an earlier encode kernel (buffer stores with
-# out-of-range offsets and a one-tile-ahead prefetch) ended in a GPU memory
-# fault.  That kernel has been taken out, but no cause was shown, so the case
-# stays off the GPU until one is.
-@pytest.mark.parametrize("name", ["markov_1GiB", "zipf256_1GiB"])
-def test_large_1GiB_properties_and_samples(codec, name):
-    """1 GiB streams (the leading half of the 2 GiB ones) in the launch
-    configuration the bench times (1 MiB chunks, 128-byte sub-blocks): exact
-    histogram, T = sum h*len, monotone index ending at T, sampled chunks and
-    sub-block offsets against the oracle, and an exact round trip."""
-    _say(f"{name}: generate")
-    n = 1 << 30
-    chunk, sub = 1 << 20, 128
-    a = datagen.workload(name)
-    assert a.size == n
+def _full_parity(codec, a, chunk, sub, name):
+    """Compress on the GPU, then every word, chunk offset and sub-block offset
+    against the oracle (piece by piece in a thread pool), the exact histogram
+    and code, and an exact round trip."""
     x = dev(a)
     st = codec.new_status()
-    _say(f"{name}: compress")
+    _say(f"{name}: compress n={a.size} chunk={chunk} sub={sub}")
     c = codec.compress(x, chunk, sub, status=st)
     _check_status(st)
     h = host_u64(c["hist"])
@@ -403,20 +386,11 @@ def test_large_1GiB_properties_and_samples(codec, name):
     code = oracle.canonical_codes(ln)
     T = oracle.total_bits(h, ln)
     off = host_u64(c["chunk_off"])
-    assert off[0] == 0 and off[-1] == T and np.all(np.diff(off.astype(np.int64)) >= 0)
     words = host_u32(c["words"], (T + 31) // 32)
-    sub_lo = host_u32(c["sub_lo"])
-    rng = np.random.default_rng(1)
-    for ch in sorted(set(rng.integers(0, n // chunk, size=6).tolist()) | {0, n // chunk - 1}):
-        seg = a[ch * chunk:(ch + 1) * chunk]
-        w, o = oracle.encode(seg, ln, code, chunk)  # the chunk alone, with the stream's codebook
-        assert int(o[-1]) == int(off[ch + 1] - off[ch])
-        assert np.array_equal(_bits_of(words, int(off[ch]), int(off[ch + 1])), _bits_of(w, 0, int(o[-1])))
-        # the chunk's sub-block starts, shifted by the chunk's first bit
-        per = chunk // sub
-        _, fine = oracle.encode(seg, ln, code, sub)
-        want = (fine[:per].astype(np.uint64) + off[ch]) & np.uint64(0xFFFFFFFF)
-        assert np.array_equal(sub_lo[ch * per:(ch + 1) * per].astype(np.uint64), want), ch
+    sub_lo = host_u32(c["sub_lo"]) if sub else None
+    _say(f"{name}: oracle pieces")
+    assert oracle_pieces.check_stream(a, words, off, sub_lo, ln, code, chunk, sub) == T
+    del words, sub_lo
     _say(f"{name}: decode")
     out = codec.decompress(c, status=st)
     _check_status(st)
@@ -425,40 +399,39 @@ def test_large_1GiB_properties_and_samples(codec, name):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("name", ["markov_1GiB", "zipf256_1GiB"])
+def test_large_1GiB_full_parity(codec, name):
+    """1 GiB streams (the leading half of the 2 GiB ones) in the launch
+    configuration the bench times (1 MiB chunks, 128-byte sub-blocks): every
+    word and index entry against the oracle, and an exact round trip.  The
+    tile offsets cross 64 scan blocks (the segmented scan and its block
+    carries)."""
+    _say(f"{name}: generate")
+    a = datagen.workload(name)
+    assert a.size == 1 << 30
+    _full_parity(codec, a, 1 << 20, 128, name)
+
+
+@pytest.mark.parametrize("kind,n,chunk,sub", [("zipf256", 9 * (16 << 20) + 12_345, 256 << 10, 64),
+                                              ("markov", 8 * (16 << 20) + 16_384 * 3 + 7, 64 << 10, 256),
+                                              ("markov", 8 * (16 << 20), 1 << 20, 128)])
+def test_scan_blocks_beyond_inline_carry(codec, kind, n, chunk, sub):
+    """Streams just past the eight scan blocks (1024 tiles each) whose carries
+    one launch sums, and exactly at that edge: full parity."""
+    a = _data(kind, n, seed=3)
+    _full_parity(codec, a, chunk, sub, f"{kind} {n}")
+
+
+# The 2 GiB case: one run of this test, against an earlier encode kernel
+# (buffer stores whose lanes with nothing to store gave an offset past the
+# buffer's range, and a one-tile-ahead prefetch), ended in a GPU memory fault.
+# That kernel has been taken out, but no cause was shown, so the case stays
+# off the GPU until one is.
 @pytest.mark.skip(reason="GPU memory fault in a run of this case; cause not yet shown, case kept off the GPU")
 @pytest.mark.parametrize("name", ["markov_2GiB", "zipf256_2GiB"])
-def test_full_size_2GiB_properties_and_samples(codec, name):
-    """2 GiB streams: exact histogram, T = sum h*len, monotone index ending at
-    T, sampled chunks re-encoded by the oracle, and an exact round trip."""
+def test_full_size_2GiB(codec, name):
+    """2 GiB streams in the configuration of the run that faulted (1 MiB
+    chunks, 4096-byte sub-blocks, so the direct decoder): full parity."""
     _say(f"{name}: generate")
-    n = 1 << 31
-    chunk = 1 << 20
     a = datagen.workload(name)
-    x = dev(a)
-    st = codec.new_status()
-    _say(f"{name}: compress")
-    c = codec.compress(x, chunk, 4096, status=st)
-    _check_status(st)
-    h = host_u64(c["hist"])
-    assert np.array_equal(h, np.bincount(a, minlength=256).astype(np.uint64))
-    ln = oracle.code_lengths(h)
-    code = oracle.canonical_codes(ln)
-    T = oracle.total_bits(h, ln)
-    off = host_u64(c["chunk_off"])
-    assert off[0] == 0 and off[-1] == T and np.all(np.diff(off.astype(np.int64)) >= 0)
-    nw = (T + 31) // 32
-    words = host_u32(c["words"], nw)
-    rng = np.random.default_rng(0)
-    for ch in sorted(set(rng.integers(0, n // chunk, size=6).tolist()) | {0, n // chunk - 1}):
-        seg = a[ch * chunk:(ch + 1) * chunk]
-        w, o = oracle.encode(seg, ln, code, chunk)
-        assert int(o[-1]) == int(off[ch + 1] - off[ch])
-        want = _bits_of(w, 0, int(o[-1]))
-        got = _bits_of(words, int(off[ch]), int(off[ch + 1]))
-        assert np.array_equal(got, want), ch
-    _say(f"{name}: decode")
-    out = codec.decompress(c, status=st)
-    _check_status(st)
-    assert torch.equal(out, x)
-    del out, x, c
-    torch.cuda.empty_cache()
+    _full_parity(codec, a, 1 << 20, 4096, name)
