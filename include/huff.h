@@ -66,7 +66,8 @@ enum {
     HUFF_E_AGAIN = -5,    /* server: request still pending */
     HUFF_E_HIP = -6,      /* a HIP runtime call failed */
     HUFF_E_CODELEN = -7,  /* a code would be longer than 63 bits */
-    HUFF_E_NOTFOUND = -8  /* server: unknown ticket or stream handle */
+    HUFF_E_NOTFOUND = -8, /* server: unknown ticket or stream handle */
+    HUFF_E_MISMATCH = -9  /* server: the result differs from the expected result the request carried */
 };
 
 #define HUFF_MAX_CODE_LEN 63
@@ -312,6 +313,14 @@ typedef struct huff_request {
     const uint8_t* d_in;    /* compress: device input of n bytes, caller-owned until the request is done */
     uint64_t n;             /* compress: input length */
     uint64_t stream_handle; /* decode: a resident stream (result of a finished compress) */
+    /* Optional check of the result on the device (NULL: none).  Once the
+       request has run, its result is compared with d_expect: for a compress,
+       the stream must be expect_bits long and its ceil(expect_bits/32) words
+       must equal those at d_expect; for a decode, the n decoded bytes must
+       equal those at d_expect.  A difference sets the result's status to
+       HUFF_E_MISMATCH.  d_expect is caller-owned until the request is done. */
+    const void* d_expect;
+    uint64_t expect_bits;   /* compress with d_expect: the expected total bits T */
 } huff_request;
 
 typedef struct huff_result {

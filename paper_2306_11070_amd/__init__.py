@@ -51,6 +51,15 @@ def encoded_bits(hist, cb: HuffCodebook) -> int:
     return int(lib().huff_encoded_bits(h.ctypes.data, ctypes.byref(cb)))
 
 
+def _struct_dtype(cls) -> np.dtype:
+    """numpy dtype with the field offsets and size of a ctypes struct."""
+    kinds = {ctypes.c_int32: "<i4", ctypes.c_uint32: "<u4", ctypes.c_uint64: "<u8", ctypes.c_void_p: "<u8",
+             ctypes.c_double: "<f8"}
+    names = [f for f, _ in cls._fields_]
+    return np.dtype({"names": names, "formats": [kinds[t] for _, t in cls._fields_],
+                     "offsets": [getattr(cls, f).offset for f in names], "itemsize": ctypes.sizeof(cls)})
+
+
 def dcb_to_host(dcb) -> HuffDcb:
     """Copies a device codebook tensor back and parses it (synchronises)."""
     raw = dcb.detach().cpu().numpy().tobytes()
@@ -382,17 +391,24 @@ class Server:
     def _res(r: HuffResult) -> dict:
         return {k: getattr(r, k) for k, _ in HuffResult._fields_}
 
-    def submit_compress(self, x) -> int:
+    def submit_compress(self, x, expect=None, expect_bits: int = 0) -> int:
+        """Queues a compress of x.  With `expect` (device tensor of the
+        expected stream words) and `expect_bits` (expected T), the server
+        compares the result on the device (status HUFF_E_MISMATCH if it
+        differs)."""
         t = ctypes.c_uint64()
-        req = HuffRequest(HUFF_OP_COMPRESS, 0, _ptr(x), x.numel(), 0)
+        req = HuffRequest(HUFF_OP_COMPRESS, 0, _ptr(x), x.numel(), 0, _ptr(expect), expect_bits)
         _check(lib().huff_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "huff_server_submit")
-        self._keep[t.value] = x
+        self._keep[t.value] = (x, expect)
         return t.value
 
-    def submit_decode(self, handle: int) -> int:
+    def submit_decode(self, handle: int, expect=None) -> int:
+        """Queues a decode of a resident stream; with `expect` (device tensor
+        of the expected bytes) the result is compared on the device."""
         t = ctypes.c_uint64()
-        req = HuffRequest(HUFF_OP_DECODE, 0, None, 0, handle)
+        req = HuffRequest(HUFF_OP_DECODE, 0, None, 0, handle, _ptr(expect), 0)
         _check(lib().huff_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)), "huff_server_submit")
+        self._keep[t.value] = (None, expect)
         return t.value
 
     def wait(self, ticket: int) -> dict:
@@ -419,17 +435,40 @@ class Server:
         _check(lib().huff_server_release(self._h, handle), "huff_server_release")
 
     def replay(self, requests: list, arrivals, discard=None) -> list:
-        """requests: list of (op, tensor_or_None, handle); arrivals: seconds;
-        discard: indexes whose results are freed as soon as they are done."""
+        """requests: list of (op, tensor_or_None, handle) or (op, tensor_or_None,
+        handle, expect_ptr, expect_bits) (an expected result, compared on the
+        device); arrivals: seconds; discard: indexes whose results are freed as
+        soon as they are done (True: all)."""
         n = len(requests)
         reqs = (HuffRequest * max(1, n))()
-        drop = set(discard or ())
-        for i, (op, x, h) in enumerate(requests):
-            reqs[i] = HuffRequest(op, 1 if i in drop else 0, _ptr(x), 0 if x is None else x.numel(), h or 0)
+        drop = discard if discard is True else set(discard or ())
+        for i, rq in enumerate(requests):
+            op, x, h = rq[0], rq[1], rq[2]
+            ep, eb = (rq[3], rq[4]) if len(rq) > 3 else (None, 0)
+            reqs[i] = HuffRequest(op, 1 if (drop is True or i in drop) else 0, _ptr(x), 0 if x is None else x.numel(),
+                                  h or 0, ep, eb)
         arr = np.ascontiguousarray(arrivals, dtype=np.float64)
         res = (HuffResult * max(1, n))()
         _check(lib().huff_server_replay(self._h, reqs, arr.ctypes.data, n, res), "huff_server_replay")
         return [self._res(res[i]) for i in range(n)]
+
+    @staticmethod
+    def request_array(count: int) -> np.ndarray:
+        """A zeroed numpy array laid out as `count` huff_request structs
+        (fields op, flags, d_in, n, stream_handle, d_expect, expect_bits)."""
+        return np.zeros(count, dtype=_struct_dtype(HuffRequest))
+
+    def replay_array(self, reqs: np.ndarray, arrivals) -> np.ndarray:
+        """huff_server_replay over a request_array(); returns the results as a
+        numpy array laid out as huff_result structs.  Keep the tensors the
+        requests point to alive until this returns."""
+        reqs = np.ascontiguousarray(reqs, dtype=_struct_dtype(HuffRequest))
+        arr = np.ascontiguousarray(arrivals, dtype=np.float64)
+        assert arr.size == reqs.size
+        res = np.zeros(max(1, reqs.size), dtype=_struct_dtype(HuffResult))
+        _check(lib().huff_server_replay(self._h, reqs.ctypes.data, arr.ctypes.data, reqs.size, res.ctypes.data),
+               "huff_server_replay")
+        return res[:reqs.size]
 
     def stats(self) -> dict:
         a = (ctypes.c_uint64 * 6)()

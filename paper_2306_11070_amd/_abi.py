@@ -8,9 +8,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhuff.so")
 
 ERRORS = {0: "HUFF_OK", -1: "HUFF_E_INVAL", -2: "HUFF_E_CAPACITY", -3: "HUFF_E_CORRUPT", -4: "HUFF_E_NOMEM",
-          -5: "HUFF_E_AGAIN", -6: "HUFF_E_HIP", -7: "HUFF_E_CODELEN", -8: "HUFF_E_NOTFOUND"}
+          -5: "HUFF_E_AGAIN", -6: "HUFF_E_HIP", -7: "HUFF_E_CODELEN", -8: "HUFF_E_NOTFOUND", -9: "HUFF_E_MISMATCH"}
 HUFF_OK, HUFF_E_INVAL, HUFF_E_CAPACITY, HUFF_E_CORRUPT, HUFF_E_NOMEM = 0, -1, -2, -3, -4
-HUFF_E_AGAIN, HUFF_E_HIP, HUFF_E_CODELEN, HUFF_E_NOTFOUND = -5, -6, -7, -8
+HUFF_E_AGAIN, HUFF_E_HIP, HUFF_E_CODELEN, HUFF_E_NOTFOUND, HUFF_E_MISMATCH = -5, -6, -7, -8, -9
 #: kernel ids of huff_ctx_kernel_time
 HUFF_K_HIST, HUFF_K_CODEBOOK, HUFF_K_SCAN, HUFF_K_ENCODE, HUFF_K_DECODE = 0, 1, 2, 3, 4
 KERNEL_IDS = {"hist": 0, "codebook": 1, "scan": 2, "encode": 3, "decode": 4}
@@ -56,7 +56,7 @@ class HuffServerCfg(ctypes.Structure):
 
 class HuffRequest(ctypes.Structure):
     _fields_ = [("op", ctypes.c_int32), ("flags", ctypes.c_uint32), ("d_in", ctypes.c_void_p), ("n", ctypes.c_uint64),
-                ("stream_handle", ctypes.c_uint64)]
+                ("stream_handle", ctypes.c_uint64), ("d_expect", ctypes.c_void_p), ("expect_bits", ctypes.c_uint64)]
 
 
 HUFF_REQ_DISCARD = 1

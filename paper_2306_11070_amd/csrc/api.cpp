@@ -133,6 +133,7 @@ const char* huff_strerror(huff_status s) {
         case HUFF_E_HIP: return "HIP runtime error";
         case HUFF_E_CODELEN: return "code longer than 63 bits";
         case HUFF_E_NOTFOUND: return "unknown ticket or handle";
+        case HUFF_E_MISMATCH: return "result differs from the expected result";
         default: return "unknown status";
     }
 }

@@ -126,6 +126,18 @@ struct CbArgs {
     uint8_t len[256];
 };
 
+// One result check of the request server: `bytes` bytes at `got` against
+// `want`, and (got_bits non-null) the stream length *got_bits against
+// want_bits; a difference sets *status to HUFF_E_MISMATCH.
+struct CmpJob {
+    const uint8_t* got;
+    const uint8_t* want;
+    uint64_t bytes;
+    const uint64_t* got_bits;
+    uint64_t want_bits;
+    int32_t* status;
+};
+
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s);
@@ -143,5 +155,6 @@ hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hip
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, uint32_t blocks, hipStream_t s);
 hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
+hipError_t launch_compare(const CmpJob* jobs, uint32_t njobs, uint64_t total_bytes, hipStream_t s);
 
 }  // namespace huff

@@ -1977,4 +1977,36 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long 
     return hipGetLastError();
 }
 
+// Result checks of the request server: every workgroup takes a share of
+// every job's bytes (16 bytes per lane at a time when both sides are
+// 16-byte aligned, single bytes otherwise).
+__global__ __launch_bounds__(256) void k_compare(const CmpJob* jobs, uint32_t njobs) {
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t me = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (uint32_t j = 0; j < njobs; ++j) {
+        const CmpJob c = jobs[j];
+        bool diff = false;
+        if (me == 0 && c.got_bits && *c.got_bits != c.want_bits) diff = true;
+        const bool vec = (((uintptr_t)c.got | (uintptr_t)c.want) & 15u) == 0;
+        const uint64_t nv = vec ? c.bytes >> 4 : 0;
+        const uint4* g4 = reinterpret_cast<const uint4*>(c.got);
+        const uint4* w4 = reinterpret_cast<const uint4*>(c.want);
+        for (uint64_t i = me; i < nv; i += stride) {
+            const uint4 a = g4[i], b = w4[i];
+            diff |= a.x != b.x || a.y != b.y || a.z != b.z || a.w != b.w;
+        }
+        for (uint64_t i = (nv << 4) + me; i < c.bytes; i += stride) diff |= c.got[i] != c.want[i];
+        if (diff) atomicMin(c.status, (int32_t)HUFF_E_MISMATCH);
+    }
+}
+
+hipError_t launch_compare(const CmpJob* jobs, uint32_t njobs, uint64_t total_bytes, hipStream_t s) {
+    if (njobs == 0) return hipSuccess;
+    uint64_t blocks = (total_bytes / 16 + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_compare, dim3((uint32_t)blocks), dim3(256), 0, s, jobs, njobs);
+    return hipGetLastError();
+}
+
 }  // namespace huff

@@ -174,6 +174,7 @@ struct huff_server {
     uint64_t tables_bytes(uint32_t nreq, uint64_t ntiles) const {
         return 2 * up(std::max<uint32_t>(nreq, 1) * sizeof(FileDesc), kAlign) + up(nreq * 4 + 8, kAlign) +
                up(nreq * 8 + 8, kAlign) + up(nreq * 8 + 8, kAlign) + up(std::max<uint64_t>(ntiles, 1) * 4, kAlign) +
+               up(std::max<uint32_t>(nreq, 1) * sizeof(CmpJob), kAlign) +
                up(batch_workspace_bytes(ntiles) + 4 * kAlign, kAlign);
     }
 
@@ -241,6 +242,7 @@ bool huff_server::launch(Slot& sl) {
     const uint64_t** d_lenptr = (const uint64_t**)carve(nreq * 8 + 8);
     uint64_t* d_len = (uint64_t*)carve(nreq * 8 + 8);
     uint32_t* d_tile_file = (uint32_t*)carve(std::max<uint64_t>(ntiles, 1) * 4);
+    CmpJob* d_jobs = (CmpJob*)carve(std::max<uint32_t>(nreq, 1) * sizeof(CmpJob));
     uint8_t* ws = carve(batch_workspace_bytes(ntiles) + 4 * kAlign);
     for (uint32_t i = 0; i < nreq; ++i) {
         Req* q = take[i];
@@ -313,10 +315,36 @@ bool huff_server::launch(Slot& sl) {
     BatchTables ct, dt;
     huff_status st = batch_tables(cf.data(), (uint32_t)cf.size(), cfg.chunk_size, cfg.sub_size, ct);
     if (st == HUFF_OK) st = batch_tables(df.data(), (uint32_t)df.size(), cfg.chunk_size, cfg.sub_size, dt, true);
-    // staging: [enc | dec | status zeros | length pointers | tile_file]
+    // result checks of the requests that carry an expected result
+    std::vector<CmpJob> jobs;
+    uint64_t cmp_bytes = 0;
+    for (uint32_t i = 0; i < nreq; ++i) {
+        const Req* q = sl.reqs[i];
+        if (!q->r.d_expect) continue;
+        CmpJob j;
+        memset(&j, 0, sizeof(j));
+        j.want = (const uint8_t*)q->r.d_expect;
+        j.status = d_status + i;
+        const Resident& rs = residents[q->handle];
+        if (q->r.op == HUFF_OP_COMPRESS) {
+            const uint64_t nch = (rs.n + cfg.chunk_size - 1) / cfg.chunk_size;
+            j.got = (const uint8_t*)rs.words;
+            j.bytes = (q->r.expect_bits + 31) / 32 * 4;
+            if (j.bytes > rs.nwords * 4) j.bytes = rs.nwords * 4;  // a longer expectation fails on the length
+            j.got_bits = rs.chunk_off + nch;
+            j.want_bits = q->r.expect_bits;
+        } else {
+            j.got = rs.out;
+            j.bytes = rs.n;
+        }
+        cmp_bytes += j.bytes;
+        jobs.push_back(j);
+    }
+    // staging: [enc | dec | status zeros | length pointers | tile_file | checks]
     const uint64_t sz_enc = cf.size() * sizeof(FileDesc), sz_dec = df.size() * sizeof(FileDesc);
     const uint64_t o_stat = sz_enc + sz_dec, o_lp = o_stat + up(nreq * 4, 8), o_tf = o_lp + cf.size() * 8;
-    const uint64_t need = o_tf + ct.ntiles * 4;
+    const uint64_t o_jobs = up(o_tf + ct.ntiles * 4, 8);
+    const uint64_t need = o_jobs + jobs.size() * sizeof(CmpJob);
     if (st == HUFF_OK && !grow_pinned(sl.staging, sl.staging_bytes, need)) st = HUFF_E_NOMEM;
     if (st == HUFF_OK && !grow_pinned(sl.readback, sl.readback_bytes, nreq * 4 + cf.size() * 8 + 16)) st = HUFF_E_NOMEM;
     if (st == HUFF_OK) {
@@ -330,6 +358,7 @@ bool huff_server::launch(Slot& sl) {
             lp[i] = cf[i].chunk_off + nch;
         }
         memcpy(h + o_tf, ct.tile_file.data(), ct.ntiles * 4);
+        if (!jobs.empty()) memcpy(h + o_jobs, jobs.data(), jobs.size() * sizeof(CmpJob));
         hipStream_t s = sl.stream;
         bool ok = true;
         if (sz_enc) ok = ok && hipMemcpyAsync(d_enc, h, sz_enc, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -339,6 +368,9 @@ bool huff_server::launch(Slot& sl) {
             ok = ok && hipMemcpyAsync(d_lenptr, lp, cf.size() * 8, hipMemcpyHostToDevice, s) == hipSuccess;
         if (ct.ntiles)
             ok = ok && hipMemcpyAsync(d_tile_file, h + o_tf, ct.ntiles * 4, hipMemcpyHostToDevice, s) == hipSuccess;
+        if (!jobs.empty())
+            ok = ok && hipMemcpyAsync(d_jobs, h + o_jobs, jobs.size() * sizeof(CmpJob), hipMemcpyHostToDevice, s) ==
+                           hipSuccess;
         if (!ok) st = HUFF_E_HIP;
         // the two plans over the tables block
         huff_batch pc, pd;
@@ -368,6 +400,8 @@ bool huff_server::launch(Slot& sl) {
         if (st == HUFF_OK && pc.nfiles) st = batch_launch(&pc, HUFF_OP_COMPRESS, s);
         if (st == HUFF_OK && pc.nfiles) st = hip_status(launch_gather_u64(d_lenptr, d_len, pc.nfiles, s));
         if (st == HUFF_OK && pd.nfiles) st = batch_launch(&pd, HUFF_OP_DECODE, s);
+        if (st == HUFF_OK && !jobs.empty())
+            st = hip_status(launch_compare(d_jobs, (uint32_t)jobs.size(), cmp_bytes, s));
         uint8_t* rb = (uint8_t*)sl.readback;
         if (st == HUFF_OK && hipMemcpyAsync(rb, d_status, nreq * 4, hipMemcpyDeviceToHost, s) != hipSuccess) st = HUFF_E_HIP;
         if (st == HUFF_OK && cf.size() &&

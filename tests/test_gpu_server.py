@@ -224,3 +224,51 @@ def test_server_replay_open_loop(P):
         srv.release(p["handle"])
     assert srv.stats()["mem_used"] == 0
     srv.close()
+
+
+def test_server_checks_results_against_oracle(P):
+    """Requests that carry the oracle's result are compared with it on the
+    device: equal results keep status 0; a changed word, a wrong length or a
+    changed decoded byte gives HUFF_E_MISMATCH (-9).  Also through the
+    open-loop replay with every result discarded after its check."""
+    _say("server result checks")
+    chunk, sub = 65536, 128
+    srv = P.Server(mem_budget=512 << 20, nslots=2, chunk_size=chunk, sub_size=sub)
+    data = [_req_data(i, n) for i, n in enumerate([1, 70_000, 1_000_003, 16_384, 2_500_000])]
+    refs = [oracle.compress(a, chunk) for a in data]
+    xs = [dev(a) for a in data]
+    want = [dev(np.concatenate([r["words"], np.zeros(4, np.uint32)]).view(np.int32)) for r in refs]
+    bits = [int(r["total_bits"]) for r in refs]
+    res = [srv.wait(srv.submit_compress(x, expect=w, expect_bits=b)) for x, w, b in zip(xs, want, bits)]
+    assert [r["status"] for r in res] == [0] * len(xs)
+    # a changed word, then a wrong length
+    bad = want[2].clone()
+    bad[1234] ^= 1 << 7
+    assert srv.wait(srv.submit_compress(xs[2], expect=bad, expect_bits=bits[2]))["status"] == -9
+    assert srv.wait(srv.submit_compress(xs[2], expect=want[2], expect_bits=bits[2] + 1))["status"] == -9
+    # decodes against the original bytes
+    dec = [srv.wait(srv.submit_decode(r["handle"], expect=x)) for r, x in zip(res, xs)]
+    assert [d["status"] for d in dec] == [0] * len(xs)
+    for d in dec:
+        srv.release(d["handle"])
+    wrong = xs[3].clone()
+    wrong[100] ^= 1
+    assert srv.wait(srv.submit_decode(res[3]["handle"], expect=wrong))["status"] == -9
+    # replay: every request checked, every result discarded
+    rng = np.random.default_rng(11)
+    reqs, arr, t = [], [], 0.0
+    for i in range(80):
+        k = int(rng.integers(0, len(xs)))
+        if rng.random() < 0.7:
+            reqs.append((OP_C, xs[k], 0, want[k].data_ptr(), bits[k]))
+        else:
+            reqs.append((OP_D, None, res[k]["handle"], xs[k].data_ptr(), 0))
+        t += float(rng.exponential(0.0003))
+        arr.append(t)
+    out = srv.replay(reqs, arr, discard=True)
+    assert all(r["status"] == 0 for r in out)
+    for r in res:
+        srv.release(r["handle"])
+    st = srv.stats()
+    assert st["mem_used"] == 0
+    srv.close()
