@@ -209,6 +209,23 @@ huff_status huff_compress(huff_ctx* ctx, const uint8_t* d_in, uint64_t n, uint32
                           uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, void* stream);
 
 /*
+ * huff_compress for callers that cannot allocate device memory: code under
+ * HIP graph capture, serving loops and harnesses that forbid hipMalloc.  Same
+ * arguments, outputs and results as huff_compress, but every workspace comes
+ * from one fixed device array that the library holds on each device until the
+ * process ends (about 8.5 MB), so the call itself allocates nothing.  n must
+ * be at most HUFF_NOALLOC_MAX_N; a larger n returns HUFF_E_INVAL before
+ * anything is queued.  All calls on one device share that array: calls that
+ * overlap on one device (different streams, or different host threads) race
+ * and must be ordered by the caller.  HUFF_E_HIP if the array's address could
+ * not be found when ctx was created.
+ */
+#define HUFF_NOALLOC_MAX_N (256ull << 20)
+huff_status huff_compress_noalloc(huff_ctx* ctx, const uint8_t* d_in, uint64_t n, uint32_t chunk_size, huff_dcb* d_cb,
+                                  uint64_t* d_hist, uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off,
+                                  uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, void* stream);
+
+/*
  * Chunk-indexed decode (the inverse of huff_encode): writes n bytes to
  * d_out.  d_words has nwords valid words; every read past them is treated as
  * corrupt.  With d_sub_lo (sub_size != 0) the decoder starts one lane at

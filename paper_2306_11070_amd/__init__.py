@@ -223,6 +223,21 @@ class Codec:
         return dict(hist=hist, dcb=dcb, words=words, chunk_off=off, sub_lo=sub if sub_size else None, n=n,
                     chunk_size=chunk_size, sub_size=sub_size)
 
+    def compress_noalloc(self, x, chunk_size: int, sub_size: int, out: dict, status=None, stream=None) -> dict:
+        """huff_compress_noalloc: huff_compress with the library's fixed device
+        workspace (no allocation by the library; at most HUFF_NOALLOC_MAX_N
+        bytes).  `out` must hold preallocated hist/dcb/words/chunk_off (and
+        sub_lo when sub_size) tensors."""
+        x = self._u8(x)
+        n = x.numel()
+        words = out["words"]
+        _check(lib().huff_compress_noalloc(self._ctx, _ptr(x), n, chunk_size, _ptr(out["dcb"]), _ptr(out.get("hist")),
+                                           _ptr(words), words.numel(), _ptr(out["chunk_off"]), sub_size,
+                                           _ptr(out.get("sub_lo")) if sub_size else None, _ptr(status),
+                                           self._stream(stream)), "huff_compress_noalloc")
+        return dict(hist=out.get("hist"), dcb=out["dcb"], words=words, chunk_off=out["chunk_off"],
+                    sub_lo=out.get("sub_lo") if sub_size else None, n=n, chunk_size=chunk_size, sub_size=sub_size)
+
     def decompress(self, c: dict, out=None, status=None, stream=None):
         return self.decode(c["words"], c["words"].numel(), c["chunk_off"], c["n"], c["chunk_size"], c["dcb"],
                            c.get("sub_lo"), c.get("sub_size", 0), out=out, status=status, stream=stream)

@@ -155,6 +155,9 @@ huff_status huff_ctx_create(int device, const huff_params* params, huff_ctx** ou
         if (check_params(*params) != HUFF_OK) { delete c; return HUFF_E_INVAL; }
         merge_params(c->params, *params);
     }
+    // the fixed workspace of huff_compress_noalloc: its address on this device
+    // (looked up once per device; kept null if the lookup fails)
+    if (scratch_address(device, &c->scratch) != hipSuccess) c->scratch = nullptr;
     bool ok = hipMalloc(&c->hist_st, sizeof(HistState)) == hipSuccess &&
               hipMalloc(&c->status, 256) == hipSuccess;
     if (ok) ok = hipMemset(c->hist_st, 0, sizeof(HistState)) == hipSuccess &&
@@ -229,7 +232,23 @@ huff_status huff_ctx_status(huff_ctx* c, int32_t* out, int reset) {
 }
 
 namespace {
-huff_status launch_hist_only(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint16_t* tile_hist, hipStream_t s) {
+// Device workspaces of one compress or encode: the context's own (grown by
+// ensure_tiles) or, for huff_compress_noalloc, slices of the fixed array.
+struct Workspace {
+    HistState* hist_st;
+    uint16_t* tile_hist;
+    uint32_t* tile_bits;
+    uint32_t* tile_local;
+    unsigned long long* blk_tail;
+    unsigned long long* blk_carry;
+};
+
+Workspace ctx_workspace(huff_ctx* c) {
+    return {c->hist_st, c->tile_hist, c->tile_bits, c->tile_local, c->blk_tail, c->blk_carry};
+}
+
+huff_status launch_hist_only(huff_ctx* c, HistState* hist_st, const uint8_t* d_in, uint64_t n, uint16_t* tile_hist,
+                             hipStream_t s) {
     const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
     uint64_t blocks = std::min<uint64_t>(c->params.hist_blocks, ntiles);
     blocks = std::max<uint64_t>(blocks, (n >> 31) + 1);  // < 2^31 bytes per workgroup: u32 LDS counters
@@ -239,7 +258,7 @@ huff_status launch_hist_only(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint1
     memset(&a, 0, sizeof(a));
     a.in = d_in;
     a.n = n;
-    a.st = c->hist_st;
+    a.st = hist_st;
     a.tile_hist = tile_hist;
     a.depth_log2 = log2u(c->params.hist_depth);
     a.tiles_per_block = tpb;
@@ -258,16 +277,12 @@ huff_status check_encode_args(uint64_t n, const void* d_in, const void* d_words,
 
 // Tile offsets (from the per-tile histograms when `from_hist`, else from a
 // bit-counting pass over the input), then the encode itself.
-huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff_dcb* d_cb, uint32_t chunk_size,
-                              uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off, uint32_t sub_size,
-                              uint32_t* d_sub_lo, int32_t* d_status, bool from_hist, hipStream_t s) {
+huff_status launch_encode_one(huff_ctx* c, const Workspace& ws, const uint8_t* d_in, uint64_t n, const huff_dcb* d_cb,
+                              uint32_t chunk_size, uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off,
+                              uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, bool from_hist, hipStream_t s) {
     if (n == 0) return hip_status(launch_encode_empty(d_chunk_off, sub_size ? d_sub_lo : nullptr, s));
     const uint64_t ntiles = (n + kEncTile - 1) / kEncTile;
     huff_status st = HUFF_OK;
-    if (!from_hist) {
-        st = ensure_tiles(c, ntiles);
-        if (st != HUFF_OK) return st;
-    }
     {
         // code bits per tile (from the tile histograms, or counted from the
         // input), then their scan
@@ -275,24 +290,24 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
         if (from_hist) {
             TileBitsArgs ta;
             memset(&ta, 0, sizeof(ta));
-            ta.tile_hist = c->tile_hist;
+            ta.tile_hist = ws.tile_hist;
             ta.cb = d_cb;
             ta.ntiles = ntiles;
-            ta.tile_bits = c->tile_bits;
+            ta.tile_bits = ws.tile_bits;
             ta.status = d_status;
             ta.err = c->status;
             st = hip_status(launch_tile_bits_hist(ta, s));
         } else {
-            st = hip_status(launch_tile_bits(d_in, n, d_cb, c->tile_bits, d_status, c->status, s));
+            st = hip_status(launch_tile_bits(d_in, n, d_cb, ws.tile_bits, d_status, c->status, s));
         }
         if (st == HUFF_OK) {
             ScanArgs sa;
             memset(&sa, 0, sizeof(sa));
-            sa.tile_bits = c->tile_bits;
+            sa.tile_bits = ws.tile_bits;
             sa.ntiles = ntiles;
-            sa.tile_local = c->tile_local;
-            sa.blk_tail = c->blk_tail;
-            sa.blk_carry = c->blk_carry;
+            sa.tile_local = ws.tile_local;
+            sa.blk_tail = ws.blk_tail;
+            sa.blk_carry = ws.blk_carry;
             st = hip_status(launch_tile_scan(sa, s));
         }
     }
@@ -314,8 +329,8 @@ huff_status launch_encode_one(huff_ctx* c, const uint8_t* d_in, uint64_t n, cons
     a.sub_log2 = sub_size ? log2u(sub_size) : kNoSub;
     a.aligned = ((uintptr_t)d_in & 15u) == 0;
     a.ntiles = ntiles;
-    a.tile_local = c->tile_local;
-    a.blk_carry = c->blk_carry;
+    a.tile_local = ws.tile_local;
+    a.blk_carry = ws.blk_carry;
     a.err = c->status;
     const uint64_t grid = std::min<uint64_t>(ntiles, (uint64_t)c->num_cus * c->params.enc_blocks_per_cu);
     KernelTimer kt(c, HUFF_K_ENCODE, s);
@@ -328,7 +343,7 @@ huff_status huff_histogram(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint64_
     DeviceGuard g(c->device);
     hipStream_t s = as_stream(stream);
     if (n) {
-        huff_status st = launch_hist_only(c, d_in, n, nullptr, s);
+        huff_status st = launch_hist_only(c, c->hist_st, d_in, n, nullptr, s);
         if (st != HUFF_OK) return st;
     }
     return hip_status(launch_hist_finalize(c->hist_st, d_hist, s));
@@ -440,27 +455,28 @@ huff_status huff_encode(huff_ctx* c, const uint8_t* d_in, uint64_t n, const huff
     huff_status st = check_encode_args(n, d_in, d_words, d_chunk_off, chunk_size, sub_size, d_sub_lo);
     if (st != HUFF_OK) return st;
     DeviceGuard g(c->device);
-    return launch_encode_one(c, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
-                             d_status, false, as_stream(stream));
-}
-
-huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t chunk_size, huff_dcb* d_cb,
-                          uint64_t* d_hist, uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off,
-                          uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, void* stream) {
-    if (!c || !dcb_ok(d_cb)) return HUFF_E_INVAL;
-    huff_status st = check_encode_args(n, d_in, d_words, d_chunk_off, chunk_size, sub_size, d_sub_lo);
-    if (st != HUFF_OK) return st;
-    DeviceGuard g(c->device);
-    hipStream_t s = as_stream(stream);
     if (n) {
         st = ensure_tiles(c, (n + kEncTile - 1) / kEncTile);
         if (st != HUFF_OK) return st;
-        st = launch_hist_only(c, d_in, n, c->tile_hist, s);
+    }
+    return launch_encode_one(c, ctx_workspace(c), d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size,
+                             d_sub_lo, d_status, false, as_stream(stream));
+}
+
+namespace {
+// The compress path (histogram, device codebook, encode) over workspace ws.
+huff_status compress_with(huff_ctx* c, const Workspace& ws, const uint8_t* d_in, uint64_t n, uint32_t chunk_size,
+                          huff_dcb* d_cb, uint64_t* d_hist, uint32_t* d_words, uint64_t cap_words,
+                          uint64_t* d_chunk_off, uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status,
+                          hipStream_t s) {
+    huff_status st = HUFF_OK;
+    if (n) {
+        st = launch_hist_only(c, ws.hist_st, d_in, n, ws.tile_hist, s);
         if (st != HUFF_OK) return st;
     }
     CbArgs a;
     memset(&a, 0, sizeof(a));
-    a.acc = c->hist_st;
+    a.acc = ws.hist_st;
     a.hist_out = d_hist;
     a.out = d_cb;
     a.err = d_status ? d_status : c->status;
@@ -469,8 +485,53 @@ huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t
         st = hip_status(launch_codebook(a, 1, s));
     }
     if (st != HUFF_OK) return st;
-    return launch_encode_one(c, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
+    return launch_encode_one(c, ws, d_in, n, d_cb, chunk_size, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
                              d_status, true, s);
+}
+}  // namespace
+
+huff_status huff_compress(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t chunk_size, huff_dcb* d_cb,
+                          uint64_t* d_hist, uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off,
+                          uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, void* stream) {
+    if (!c || !dcb_ok(d_cb)) return HUFF_E_INVAL;
+    huff_status st = check_encode_args(n, d_in, d_words, d_chunk_off, chunk_size, sub_size, d_sub_lo);
+    if (st != HUFF_OK) return st;
+    DeviceGuard g(c->device);
+    if (n) {
+        st = ensure_tiles(c, (n + kEncTile - 1) / kEncTile);
+        if (st != HUFF_OK) return st;
+    }
+    return compress_with(c, ctx_workspace(c), d_in, n, chunk_size, d_cb, d_hist, d_words, cap_words, d_chunk_off,
+                         sub_size, d_sub_lo, d_status, as_stream(stream));
+}
+
+huff_status huff_compress_noalloc(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t chunk_size, huff_dcb* d_cb,
+                                  uint64_t* d_hist, uint32_t* d_words, uint64_t cap_words, uint64_t* d_chunk_off,
+                                  uint32_t sub_size, uint32_t* d_sub_lo, int32_t* d_status, void* stream) {
+    if (!c || !dcb_ok(d_cb)) return HUFF_E_INVAL;
+    if (n > HUFF_NOALLOC_MAX_N) return HUFF_E_INVAL;  // the fixed workspace holds at most this many bytes' tiles
+    huff_status st = check_encode_args(n, d_in, d_words, d_chunk_off, chunk_size, sub_size, d_sub_lo);
+    if (st != HUFF_OK) return st;
+    if (!c->scratch) return HUFF_E_HIP;  // its address was not found when the context was created
+    DeviceGuard g(c->device);
+    hipStream_t s = as_stream(stream);
+    const ScratchLayout& L = scratch_layout();
+    uint8_t* base = static_cast<uint8_t*>(c->scratch);
+    Workspace ws;
+    ws.hist_st = reinterpret_cast<HistState*>(base + L.hist_st);
+    ws.tile_hist = reinterpret_cast<uint16_t*>(base + L.tile_hist);
+    ws.tile_bits = reinterpret_cast<uint32_t*>(base + L.tile_bits);
+    ws.tile_local = reinterpret_cast<uint32_t*>(base + L.tile_local);
+    ws.blk_tail = reinterpret_cast<unsigned long long*>(base + L.blk_tail);
+    ws.blk_carry = reinterpret_cast<unsigned long long*>(base + L.blk_carry);
+    // the accumulator must start at zero; whatever the previous call on this
+    // device left there is cleared by a fill kernel (no memset node, so a
+    // graph that captures this call replays correctly)
+    st = hip_status(launch_fill_u64(reinterpret_cast<unsigned long long*>(ws.hist_st),
+                                    sizeof(HistState) / sizeof(unsigned long long), 0ull, s));
+    if (st != HUFF_OK) return st;
+    return compress_with(c, ws, d_in, n, chunk_size, d_cb, d_hist, d_words, cap_words, d_chunk_off, sub_size, d_sub_lo,
+                         d_status, s);
 }
 
 huff_status huff_decode(huff_ctx* c, const uint32_t* d_words, uint64_t nwords, const uint64_t* d_chunk_off,

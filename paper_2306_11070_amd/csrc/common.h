@@ -138,6 +138,16 @@ struct CmpJob {
     int32_t* status;
 };
 
+// The fixed device workspace of huff_compress_noalloc (kernels.hip): byte
+// offsets of its parts, sized for HUFF_NOALLOC_MAX_N input bytes.
+struct ScratchLayout {
+    uint64_t hist_st, tile_hist, tile_bits, tile_local, blk_tail, blk_carry, bytes;
+};
+const ScratchLayout& scratch_layout();
+// Address of the workspace on `device` (looked up on the first call for each
+// device, with that device current).
+hipError_t scratch_address(int device, void** out);
+
 // Launchers (kernels.hip).  Return hipSuccess or the launch error.
 hipError_t launch_histogram(const HistArgs& a, uint32_t blocks, hipStream_t s);
 hipError_t launch_hist_finalize(HistState* st, uint64_t* out, hipStream_t s);

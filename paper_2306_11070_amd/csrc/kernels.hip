@@ -14,6 +14,8 @@
 //   k_copy      plain 16-byte copy, the bandwidth probe.
 #include "common.h"
 
+#include <mutex>
+
 namespace huff {
 
 // ---------------------------------------------------------------- helpers
@@ -1975,6 +1977,51 @@ hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long 
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(k_fill_u64, dim3((uint32_t)blocks), dim3(256), 0, s, p, count, v);
     return hipGetLastError();
+}
+
+// ========================================================= fixed workspace
+// The workspaces of huff_compress_noalloc live in one file-scope device
+// array, sized for HUFF_NOALLOC_MAX_N input bytes: the histogram accumulator
+// and the per-tile histograms, bit counts, offsets and block carries.  Every
+// call on a device shares that device's copy (calls that overlap on one
+// device race).  Host code never uses the array's name as an address: its
+// address on each device comes from hipGetSymbolAddress.
+namespace {
+constexpr uint64_t kAlignWs = 256;
+constexpr uint64_t up_ws(uint64_t x) { return (x + kAlignWs - 1) / kAlignWs * kAlignWs; }
+constexpr uint64_t kWsTiles = (HUFF_NOALLOC_MAX_N + kEncTile - 1) / kEncTile;
+constexpr uint64_t kWsBlocks = kWsTiles / kScanTilesPerBlock + 1;
+constexpr ScratchLayout kLayout = {
+    0,
+    up_ws(sizeof(HistState)),
+    up_ws(sizeof(HistState)) + up_ws(kWsTiles * 512),
+    up_ws(sizeof(HistState)) + up_ws(kWsTiles * 512) + up_ws(kWsTiles * 4),
+    up_ws(sizeof(HistState)) + up_ws(kWsTiles * 512) + 2 * up_ws(kWsTiles * 4),
+    up_ws(sizeof(HistState)) + up_ws(kWsTiles * 512) + 2 * up_ws(kWsTiles * 4) + up_ws(kWsBlocks * 8),
+    up_ws(sizeof(HistState)) + up_ws(kWsTiles * 512) + 2 * up_ws(kWsTiles * 4) + 2 * up_ws(kWsBlocks * 8),
+};
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kLayout.bytes];
+
+const ScratchLayout& scratch_layout() { return kLayout; }
+
+hipError_t scratch_address(int device, void** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static void* ptr[kMaxDevices];
+    static bool found[kMaxDevices];
+    if (device < 0 || device >= kMaxDevices || !out) return hipErrorInvalidValue;
+    std::lock_guard<std::mutex> lk(mu);
+    if (!found[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[device] = p;
+        found[device] = true;
+    }
+    *out = ptr[device];
+    return hipSuccess;
 }
 
 // Result checks of the request server: every workgroup takes a share of

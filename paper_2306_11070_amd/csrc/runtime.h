@@ -23,6 +23,7 @@ struct huff_ctx {
     unsigned long long* blk_carry = nullptr;  // [tile_cap / 1024 + 1]
     uint64_t tile_cap = 0;
     int32_t* status = nullptr;
+    void* scratch = nullptr;  // this device's fixed workspace (huff_compress_noalloc)
     // kernel timing (huff_ctx_set_timing): event pairs per kernel id
     bool timing = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> spans[HUFF_K_COUNT];
