@@ -4,8 +4,9 @@ codec's arithmetic.
 
 The paper evaluates Huffman coding on a 45 MB English book corpus
 (Section III.A).  That corpus is not available, so these generators stand in
-for it (order-2 Markov text over the 96 printable symbols, and i.i.d. Zipf
-bytes).  The C source is ``gen.c``; ``build()`` compiles it with gcc.
+for it (order-2 Markov text over the 96 printable symbols, word-level text
+from a seeded Zipf vocabulary, and i.i.d. Zipf bytes).  The C source is
+``gen.c``; ``build()`` compiles it with gcc.
 """
 from __future__ import annotations
 
@@ -53,6 +54,14 @@ def _load():
     lib.gen_markov.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_double,
                                ctypes.c_double, u8p, ctypes.c_uint64, ctypes.c_uint64]
     lib.gen_markov.restype = ctypes.c_int
+    lib.gen_words_scratch_bytes.argtypes = [ctypes.c_uint32, ctypes.c_uint32]
+    lib.gen_words_scratch_bytes.restype = ctypes.c_uint64
+    lib.gen_words_vocab.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p]
+    lib.gen_words_vocab.restype = ctypes.c_int
+    lib.gen_words.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_double, ctypes.c_uint32,
+                              ctypes.c_uint32, ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_uint64,
+                              ctypes.c_uint64]
+    lib.gen_words.restype = ctypes.c_int
     lib.gen_file_params.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint64,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_uint32, ctypes.c_uint32,
                                     ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double),
@@ -142,6 +151,25 @@ def markov(n: int, seed: int, s: float = 1.0, line_mu: float = 70.0, line_sigma:
     return buf
 
 
+def words(n: int, seed: int, s: float = 1.0, vocab: int = 8192, max_word: int = 8, line_mu: float = 70.0,
+          line_sigma: float = 15.0, out=None) -> np.ndarray:
+    """n bytes of word-level text: words drawn i.i.d. Zipf(s) from a seeded
+    vocabulary of lowercase words, separated by spaces, lines broken after
+    about N(70, 15) characters."""
+    lib = _load()
+    scratch = np.empty(lib.gen_words_scratch_bytes(vocab, max_word), dtype=np.uint8)
+    assert lib.gen_words_vocab(seed, vocab, max_word, scratch.ctypes.data) == 0
+    buf = _out(n, out)
+    ptr = buf.ctypes.data
+
+    def run(lo, hi):
+        rc = lib.gen_words(ptr, n, seed, s, vocab, max_word, line_mu, line_sigma, scratch.ctypes.data, lo, hi)
+        assert rc == 0
+
+    _blocks(n, run)
+    return buf
+
+
 def file_params(seed: int, i: int, size_lo: int = 4096, size_hi: int = 1 << 24, s_lo: float = 0.6,
                 s_hi: float = 1.6, k_lo: int = 16, k_hi: int = 256):
     """(size, zipf exponent, alphabet size) of file ``i`` of a batched set."""
@@ -169,6 +197,8 @@ WORKLOADS = {
     "zipf256_2GiB": dict(n=1 << 31, chunk=None),
     "markov_1GiB": dict(n=1 << 30, chunk=None),   # the leading 2^30 bytes of markov_2GiB
     "zipf256_1GiB": dict(n=1 << 30, chunk=None),  # the leading 2^30 bytes of zipf256_2GiB
+    "words_45MiB": dict(n=45 << 20, chunk=256 << 10),  # word-level text, the block transform's workload
+    "words_1GiB": dict(n=1 << 30, chunk=None),
 }
 
 
@@ -184,4 +214,6 @@ def workload(name: str, n: int | None = None, out=None) -> np.ndarray:
         return markov(n, 3, out=out)
     if name in ("zipf256_2GiB", "zipf256_1GiB"):
         return zipf_iid(n, 4, 0.8, A256, out=out)
+    if name in ("words_45MiB", "words_1GiB"):
+        return words(n, 7, out=out)
     raise KeyError(name)

@@ -9,7 +9,9 @@
  *   - an order-2 byte Markov chain over the 96 printable symbols (newline and
  *     0x20..0x7E), each transition row a Zipf(s) distribution over its own
  *     seeded permutation of the alphabet, with a newline forced after a line
- *     length drawn from a rounded normal distribution.
+ *     length drawn from a rounded normal distribution;
+ *   - word-level text: words drawn i.i.d. Zipf(s) from a seeded vocabulary of
+ *     lowercase words, separated by spaces, lines broken as above.
  *
  * Random numbers: xoshiro256** (Blackman & Vigna, "Scrambled linear
  * pseudorandom number generators", 2018) seeded through SplitMix64
@@ -204,4 +206,71 @@ void gen_file_params(uint64_t seed, uint32_t i, uint64_t size_lo, uint64_t size_
     *size = (uint64_t)v;
     *s = s_lo + (s_hi - s_lo) * rng_unit(&r);
     *k = k_lo + (uint32_t)(rng_next(&r) % (uint64_t)(k_hi - k_lo + 1));
+}
+
+/*
+ * Word-level text.  The vocabulary (seed, its own stream) holds `vocab`
+ * words of 1..`max_word` lowercase letters: lengths uniform, letters Zipf(1.0)
+ * over a seeded permutation of 'a'..'z'.  Text: word ranks drawn Zipf(s)
+ * (rank 1 = vocabulary word 0), one space between words, and a newline in
+ * place of the space once the line has reached a length drawn as in
+ * gen_markov.  Every generation block starts a new line with a fresh word.
+ * `scratch` holds vocab * (max_word + 1) bytes plus 8 * vocab bytes (the
+ * cumulative word distribution) and may be shared by the threads that fill
+ * different blocks only if every thread filled it the same way first.
+ */
+uint64_t gen_words_scratch_bytes(uint32_t vocab, uint32_t max_word) {
+    return (uint64_t)vocab * (max_word + 1) + 8ull * vocab;
+}
+
+int gen_words_vocab(uint64_t seed, uint32_t vocab, uint32_t max_word, uint8_t* scratch) {
+    if (vocab == 0 || max_word == 0 || max_word > 64 || !scratch) return -1;
+    uint8_t letters[26], perm[26];
+    for (int i = 0; i < 26; ++i) letters[i] = (uint8_t)('a' + i);
+    gen_permutation(letters, 26, seed, 0x500000000ull, perm);
+    double lcdf[26];
+    zipf_cdf(1.0, 26, lcdf);
+    rng_t r;
+    rng_seed(&r, seed, 0x600000000ull);
+    uint8_t* words = scratch;  /* word w: length byte, then its letters */
+    for (uint32_t w = 0; w < vocab; ++w) {
+        uint8_t* p = words + (uint64_t)w * (max_word + 1);
+        const uint32_t len = 1 + (uint32_t)(rng_next(&r) % max_word);
+        p[0] = (uint8_t)len;
+        for (uint32_t k = 0; k < len; ++k) p[1 + k] = perm[cdf_pick(lcdf, 26, rng_unit(&r))];
+    }
+    return 0;
+}
+
+int gen_words(uint8_t* out, uint64_t n, uint64_t seed, double s, uint32_t vocab, uint32_t max_word, double line_mu,
+              double line_sigma, const uint8_t* scratch, uint64_t blk_lo, uint64_t blk_hi) {
+    if (vocab == 0 || max_word == 0 || max_word > 64 || (n && (!out || !scratch))) return -1;
+    const uint8_t* words = scratch;
+    double* cdf = (double*)malloc(sizeof(double) * vocab);
+    if (!cdf) return -1;
+    zipf_cdf(s, vocab, cdf);
+    for (uint64_t b = blk_lo; b < blk_hi; ++b) {
+        uint64_t lo = b * (uint64_t)GEN_BLOCK;
+        if (lo >= n) break;
+        uint64_t hi = lo + GEN_BLOCK < n ? lo + GEN_BLOCK : n;
+        rng_t r;
+        rng_seed(&r, seed, 0x700000000ull + b);
+        uint32_t line = draw_line_len(&r, line_mu, line_sigma), run = 0;
+        uint64_t i = lo;
+        while (i < hi) {
+            const uint8_t* w = words + (uint64_t)cdf_pick(cdf, vocab, rng_unit(&r)) * (max_word + 1);
+            for (uint32_t k = 0; k < w[0] && i < hi; ++k, ++run) out[i++] = w[1 + k];
+            if (i >= hi) break;
+            if (run >= line) {
+                out[i++] = 0x0A;
+                run = 0;
+                line = draw_line_len(&r, line_mu, line_sigma);
+            } else {
+                out[i++] = 0x20;
+                ++run;
+            }
+        }
+    }
+    free(cdf);
+    return 0;
 }

@@ -24,6 +24,11 @@ itself (see ``tests/test_oracle.py``):
   encode             pinned: hand-derived bitstream, string-concatenation
                      re-encoding, T = sum(h*len), chunk independence
   decode             pinned: round trip, corruption cases
+  bwt / unbwt        pinned: the Burrows-Wheeler worked examples (tests/golden),
+                     brute-force sorted rotations on small blocks, inverse
+                     round trip, permutation of each block
+  mtf / unmtf        pinned: a worked example from the standard description
+                     (tests/golden), runs give zeros, round trip
 """
 from __future__ import annotations
 
@@ -50,7 +55,8 @@ class OracleError(RuntimeError):
 def build() -> str:
     """Compile the oracle library in place (always recompiles)."""
     tmp = _LIB + ".tmp"
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-shared", "-fPIC", "-o", tmp, _SRC,
+                           os.path.join(_HERE, "bwt.c")])
     os.replace(tmp, _LIB)
     return _LIB
 
@@ -71,8 +77,14 @@ def _load():
     lib.oracle_total_bits.restype = u64
     lib.oracle_encode.argtypes = [vp, u64, vp, vp, u64, vp, u64, vp]
     lib.oracle_decode.argtypes = [vp, u64, vp, u64, u64, vp, vp]
+    u32 = ctypes.c_uint32
+    lib.oracle_bwt.argtypes = [vp, u64, u32, u32, vp, vp]
+    lib.oracle_unbwt.argtypes = [vp, u64, u32, u32, vp, vp]
+    lib.oracle_mtf.argtypes = [vp, u64, u32, vp]
+    lib.oracle_unmtf.argtypes = [vp, u64, u32, vp]
     for f in ("oracle_histogram", "oracle_code_lengths", "oracle_code_lengths_twoqueue",
-              "oracle_canonical_codes", "oracle_encode", "oracle_decode"):
+              "oracle_canonical_codes", "oracle_encode", "oracle_decode", "oracle_bwt", "oracle_unbwt",
+              "oracle_mtf", "oracle_unmtf"):
         getattr(lib, f).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -164,4 +176,50 @@ def compress(data, chunk: int, sub: int | None = None) -> dict:
         else:
             _, fine = encode(a, ln, cd, sub)
             out["sub_lo"] = sub_index(fine)
+    return out
+
+
+# ---- Method 3: block transform before the Huffman code (oracle/bwt.c) ----
+def bwt(data, block: int, every: int):
+    """Burrows-Wheeler transform block by block.  Returns (last, rows):
+    last[i] the last-column byte, rows[j] the sorted row of the rotation that
+    starts at byte j*every (within its block); rows has ceil(n/every) entries
+    and rows[b*block/every] is block b's primary index."""
+    a = _u8(data)
+    last = np.zeros(a.size, dtype=np.uint8)
+    rows = np.zeros((a.size + every - 1) // every, dtype=np.uint32)
+    _check(_load().oracle_bwt(_p(a), a.size, block, every, _p(last), _p(rows)), "bwt")
+    return last, rows
+
+
+def unbwt(last, block: int, every: int, rows) -> np.ndarray:
+    a = _u8(last)
+    r = np.ascontiguousarray(rows, dtype=np.uint32)
+    out = np.zeros(a.size, dtype=np.uint8)
+    _check(_load().oracle_unbwt(_p(a), a.size, block, every, _p(r), _p(out)), "unbwt")
+    return out
+
+
+def mtf(data, block: int) -> np.ndarray:
+    """Move-to-front positions, the list (byte values in order) reset every `block` bytes."""
+    a = _u8(data)
+    out = np.zeros(a.size, dtype=np.uint8)
+    _check(_load().oracle_mtf(_p(a), a.size, block, _p(out)), "mtf")
+    return out
+
+
+def unmtf(data, block: int) -> np.ndarray:
+    a = _u8(data)
+    out = np.zeros(a.size, dtype=np.uint8)
+    _check(_load().oracle_unmtf(_p(a), a.size, block, _p(out)), "unmtf")
+    return out
+
+
+def compress_bwt(data, block: int, every: int, chunk: int, sub: int | None = None) -> dict:
+    """Method 3: block transform, move-to-front, then Method 1's Huffman code
+    over the whole transformed stream (chunk index as Method 2's segment ids)."""
+    last, rows = bwt(data, block, every)
+    m = mtf(last, block)
+    out = compress(m, chunk, sub)
+    out.update(last=last, rows=rows, mtf=m)
     return out
