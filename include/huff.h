@@ -246,6 +246,52 @@ huff_status huff_decode(huff_ctx* ctx, const uint32_t* d_words, uint64_t nwords,
 huff_status huff_copy(huff_ctx* ctx, const void* d_src, void* d_dst, uint64_t bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Method 3 (Section III.A): a block transform before the Huffman code.  The
+ * input is cut into blocks; each block's cyclic rotations are sorted and
+ * their last column kept (the Burrows-Wheeler transform), which gathers
+ * equal bytes into runs; the last column is then move-to-front coded (each
+ * byte becomes its position in a list of the 256 byte values, reset to value
+ * order at every block, and moves to the front), because a byte Huffman code
+ * of the last column alone costs exactly the bits of the input (it is a
+ * permutation of each block).  The coded positions are then compressed with
+ * huff_compress (Methods 1 and 2).  Blocks are independent, so both
+ * directions run block-parallel.
+ *
+ * Readings: rotations compare as byte strings, equal rotations (a periodic
+ * block) in start order; the inverse needs the sorted row of one rotation per
+ * block, and these calls record the row of every rotation that starts at a
+ * multiple of `every` (a decode index, like sub_lo: the inverse rebuilds each
+ * `every`-byte piece independently).
+ * ------------------------------------------------------------------------ */
+#define HUFF_BWT_MAX_BLOCK 16384u
+
+/*
+ * Forward transform of d_in[0..n) in blocks of `block` bytes (a power of two
+ * in [1024, HUFF_BWT_MAX_BLOCK]; the last block shorter).  d_last[0..n): each
+ * block's last column; d_rows[j] (j < ceil(n/every)): the sorted row (< 2^14)
+ * of the rotation that starts at byte j*every, within its block; `every` a
+ * power of two in [16, block].  d_rows[j] for j = b*block/every is block b's
+ * classic primary index.
+ */
+huff_status huff_bwt(huff_ctx* ctx, const uint8_t* d_in, uint64_t n, uint32_t block, uint32_t every, uint8_t* d_last,
+                     uint16_t* d_rows, void* stream);
+/*
+ * Inverse of huff_bwt: d_out[0..n) from d_last and d_rows (same block and
+ * every).  A row index past its block is reported as HUFF_E_CORRUPT through
+ * d_status (or the context's status word); the bytes of that piece are then
+ * unspecified.
+ */
+huff_status huff_unbwt(huff_ctx* ctx, const uint8_t* d_last, uint64_t n, uint32_t block, uint32_t every,
+                       const uint16_t* d_rows, uint8_t* d_out, int32_t* d_status, void* stream);
+/*
+ * Move-to-front coding of d_in[0..n), the list reset every `block` bytes
+ * (a power of two in [64, 2^24]): d_out[i] = position of d_in[i] in the list.
+ */
+huff_status huff_mtf(huff_ctx* ctx, const uint8_t* d_in, uint64_t n, uint32_t block, uint8_t* d_out, void* stream);
+/* Inverse of huff_mtf (same block). */
+huff_status huff_unmtf(huff_ctx* ctx, const uint8_t* d_in, uint64_t n, uint32_t block, uint8_t* d_out, void* stream);
+
+/* ------------------------------------------------------------------------
  * Batches: many independent files, each with its own histogram, codebook and
  * stream (Method 1 applied per file, as Method 2 applies it per segment).
  * A batch plan is built once on the host; its calls then launch a fixed

@@ -190,6 +190,64 @@ class Codec:
                                  self._stream(stream)), "huff_decode")
         return out
 
+    # -- Method 3: block transform before the Huffman code --------------------
+    def bwt(self, x, block: int, every: int, last=None, rows=None, stream=None):
+        """huff_bwt: (last column uint8[n], rows int16 view of u16[ceil(n/every)])."""
+        torch = _torch()
+        x = self._u8(x)
+        n = x.numel()
+        if last is None:
+            last = torch.empty(n, dtype=torch.uint8, device=self.device)
+        if rows is None:
+            rows = torch.empty(max(1, (n + every - 1) // every), dtype=torch.int16, device=self.device)
+        _check(lib().huff_bwt(self._ctx, _ptr(x), n, block, every, _ptr(last), _ptr(rows), self._stream(stream)),
+               "huff_bwt")
+        return last, rows
+
+    def unbwt(self, last, block: int, every: int, rows, out=None, status=None, stream=None):
+        torch = _torch()
+        last = self._u8(last)
+        n = last.numel()
+        if out is None:
+            out = torch.empty(n, dtype=torch.uint8, device=self.device)
+        _check(lib().huff_unbwt(self._ctx, _ptr(last), n, block, every, _ptr(rows), _ptr(out), _ptr(status),
+                                self._stream(stream)), "huff_unbwt")
+        return out
+
+    def mtf(self, x, block: int, out=None, stream=None):
+        torch = _torch()
+        x = self._u8(x)
+        if out is None:
+            out = torch.empty(x.numel(), dtype=torch.uint8, device=self.device)
+        _check(lib().huff_mtf(self._ctx, _ptr(x), x.numel(), block, _ptr(out), self._stream(stream)), "huff_mtf")
+        return out
+
+    def unmtf(self, x, block: int, out=None, stream=None):
+        torch = _torch()
+        x = self._u8(x)
+        if out is None:
+            out = torch.empty(x.numel(), dtype=torch.uint8, device=self.device)
+        _check(lib().huff_unmtf(self._ctx, _ptr(x), x.numel(), block, _ptr(out), self._stream(stream)), "huff_unmtf")
+        return out
+
+    def compress_bwt(self, x, block: int, every: int, chunk_size: int, sub_size: int = 0, status=None, stream=None,
+                     out: dict | None = None) -> dict:
+        """Method 3: huff_bwt, huff_mtf, then huff_compress of the positions.
+        `out` may hold preallocated last/rows/mtf tensors and huff_compress's."""
+        o = dict(out or {})
+        last, rows = self.bwt(x, block, every, last=o.get("last"), rows=o.get("rows"), stream=stream)
+        m = self.mtf(last, block, out=o.get("mtf"), stream=stream)
+        c = self.compress(m, chunk_size, sub_size, status=status, stream=stream, out=o)
+        c.update(last=last, rows=rows, mtf=m, block=block, every=every)
+        return c
+
+    def decompress_bwt(self, c: dict, out=None, status=None, stream=None, work: dict | None = None):
+        """Inverse of compress_bwt: huff_decode, huff_unmtf, huff_unbwt."""
+        w = dict(work or {})
+        m = self.decompress(c, out=w.get("mtf"), status=status, stream=stream)
+        last = self.unmtf(m, c["block"], out=w.get("last"), stream=stream)
+        return self.unbwt(last, c["block"], c["every"], c["rows"], out=out, status=status, stream=stream)
+
     def copy(self, src, dst, nbytes: int | None = None, stream=None):
         nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
         _check(lib().huff_copy(self._ctx, _ptr(src), _ptr(dst), nbytes, self._stream(stream)), "huff_copy")

@@ -12,6 +12,8 @@ ERRORS = {0: "HUFF_OK", -1: "HUFF_E_INVAL", -2: "HUFF_E_CAPACITY", -3: "HUFF_E_C
 HUFF_OK, HUFF_E_INVAL, HUFF_E_CAPACITY, HUFF_E_CORRUPT, HUFF_E_NOMEM = 0, -1, -2, -3, -4
 HUFF_E_AGAIN, HUFF_E_HIP, HUFF_E_CODELEN, HUFF_E_NOTFOUND, HUFF_E_MISMATCH = -5, -6, -7, -8, -9
 #: kernel ids of huff_ctx_kernel_time
+#: largest block of huff_bwt (HUFF_BWT_MAX_BLOCK)
+HUFF_BWT_MAX_BLOCK = 16384
 #: largest input of huff_compress_noalloc (HUFF_NOALLOC_MAX_N)
 HUFF_NOALLOC_MAX_N = 256 << 20
 HUFF_K_HIST, HUFF_K_CODEBOOK, HUFF_K_SCAN, HUFF_K_ENCODE, HUFF_K_DECODE = 0, 1, 2, 3, 4
@@ -96,6 +98,10 @@ PROTOTYPES = {
     "huff_compress_noalloc": (_i32, [_vp, _vp, _u64, _u32, _vp, _vp, _vp, _u64, _vp, _u32, _vp, _vp, _vp]),
     "huff_decode": (_i32, [_vp, _vp, _u64, _vp, _u64, _u32, _vp, _u32, _vp, _vp, _vp, _vp]),
     "huff_copy": (_i32, [_vp, _vp, _vp, _u64, _vp]),
+    "huff_bwt": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp, _vp, _vp]),
+    "huff_unbwt": (_i32, [_vp, _vp, _u64, _u32, _u32, _vp, _vp, _vp, _vp]),
+    "huff_mtf": (_i32, [_vp, _vp, _u64, _u32, _vp, _vp]),
+    "huff_unmtf": (_i32, [_vp, _vp, _u64, _u32, _vp, _vp]),
     "huff_abi_sizeof": (_u64, [_int]),
     "huff_batch_create": (_i32, [_vp, _vp, _u32, _u32, _u32, _vp]),
     "huff_batch_destroy": (None, [_vp]),

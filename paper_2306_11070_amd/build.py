@@ -11,7 +11,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libhuff.so")
-SOURCES = ["kernels.hip", "api.cpp", "server.cpp"]
+SOURCES = ["kernels.hip", "bwt.hip", "api.cpp", "server.cpp"]
 ARCH = "gfx950"
 
 

@@ -566,6 +566,43 @@ huff_status huff_decode(huff_ctx* c, const uint32_t* d_words, uint64_t nwords, c
     return hip_status(launch_decode(a, c->params.dec_block, ((uintptr_t)d_out & 15u) == 0, as_stream(stream)));
 }
 
+namespace {
+huff_status check_bwt_args(uint64_t n, uint32_t block, uint32_t every) {
+    if (n >= kMaxN || !is_pow2(block) || block < 1024 || block > HUFF_BWT_MAX_BLOCK) return HUFF_E_INVAL;
+    if (!is_pow2(every) || every < 16 || every > block) return HUFF_E_INVAL;
+    return HUFF_OK;
+}
+}  // namespace
+
+huff_status huff_bwt(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t block, uint32_t every, uint8_t* d_last,
+                     uint16_t* d_rows, void* stream) {
+    if (!c || check_bwt_args(n, block, every) != HUFF_OK || (n && (!d_in || !d_last || !d_rows))) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    return hip_status(launch_bwt(d_in, n, block, log2u(every), d_last, d_rows, as_stream(stream)));
+}
+
+huff_status huff_unbwt(huff_ctx* c, const uint8_t* d_last, uint64_t n, uint32_t block, uint32_t every,
+                       const uint16_t* d_rows, uint8_t* d_out, int32_t* d_status, void* stream) {
+    if (!c || check_bwt_args(n, block, every) != HUFF_OK || (n && (!d_last || !d_rows || !d_out))) return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    return hip_status(launch_unbwt(d_last, n, block, log2u(every), d_rows, d_out, d_status ? d_status : c->status,
+                                   as_stream(stream)));
+}
+
+huff_status huff_mtf(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t block, uint8_t* d_out, void* stream) {
+    if (!c || n >= kMaxN || !is_pow2(block) || block < 64 || block > (1u << 24) || (n && (!d_in || !d_out)))
+        return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    return hip_status(launch_mtf(d_in, n, block, d_out, false, as_stream(stream)));
+}
+
+huff_status huff_unmtf(huff_ctx* c, const uint8_t* d_in, uint64_t n, uint32_t block, uint8_t* d_out, void* stream) {
+    if (!c || n >= kMaxN || !is_pow2(block) || block < 64 || block > (1u << 24) || (n && (!d_in || !d_out)))
+        return HUFF_E_INVAL;
+    DeviceGuard g(c->device);
+    return hip_status(launch_mtf(d_in, n, block, d_out, true, as_stream(stream)));
+}
+
 huff_status huff_copy(huff_ctx* c, const void* d_src, void* d_dst, uint64_t bytes, void* stream) {
     if (!c || (bytes && (!d_src || !d_dst))) return HUFF_E_INVAL;
     if (bytes == 0) return HUFF_OK;

@@ -1,0 +1,368 @@
+// HIP kernels of the block transform that Method 3 of the paper applies
+// before the Huffman code (Section III.A), for gfx950 (wave64).
+//
+//   k_bwt    one workgroup per block: the block's cyclic rotations sorted by
+//            prefix doubling (position-tagged rank keys sorted in LDS), the
+//            last column out, and the row of every rotation that starts at a
+//            multiple of `every` (the inverse starts its walks there).
+//   k_mtf    one wave per block: move-to-front positions, the 256-entry list
+//            held four bytes per lane.
+//   k_unmtf  one wave per block: the inverse.
+//   k_unbwt  one workgroup per block: the last-to-first map from a stable
+//            count of the last column (wave ballots), then one walker per
+//            `every` bytes, each starting from its recorded row.
+// All of this is integer work bound by LDS and the ALUs, not by HBM.
+#include "common.h"
+
+namespace huff {
+
+namespace {
+
+constexpr int kBwtThreads = 1024;
+constexpr uint32_t kPosBits = 14;  // positions and ranks in a block of at most 2^14 bytes
+constexpr uint64_t kPosMask = (1u << kPosBits) - 1;
+constexpr uint32_t kMaxPer = HUFF_BWT_MAX_BLOCK / kBwtThreads;  // sort slots per thread
+static_assert(HUFF_BWT_MAX_BLOCK == 1u << kPosBits, "block positions fit kPosBits");
+
+__device__ __forceinline__ void lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Ascending bitonic sort of key[0..np) in LDS (np a power of two, at least
+// twice the workgroup size); every thread of the workgroup takes part.
+template <typename K>
+__device__ void lds_bitonic_sort(K* key, uint32_t np) {
+    const uint32_t tid = threadIdx.x, nt = blockDim.x;
+    for (uint32_t k = 2; k <= np; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t p = tid; p < np / 2; p += nt) {
+                const uint32_t i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                const uint32_t l = i | j;
+                const K a = key[i], b = key[l];
+                if ((a > b) == ((i & k) == 0)) {
+                    key[i] = b;
+                    key[l] = a;
+                }
+            }
+            lds_sync();
+        }
+    }
+}
+
+// Exclusive prefix maximum of v over the threads of the workgroup, in thread
+// order (0 for thread 0).
+__device__ __forceinline__ uint32_t wg_excl_max(uint32_t v, uint32_t* s_red) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d) x = max(x, y);
+    }
+    if (lane == 63) s_red[wave] = x;
+    lds_sync();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w) before = max(before, s_red[w]);
+    lds_sync();
+    const uint32_t incl = max(x, before);
+    const uint32_t up = __shfl_up(incl, 1, 64);
+    return lane ? up : before;
+}
+
+// Orders the LDS accesses of one wave: what its lanes wrote before is seen
+// by all of its lanes after.
+__device__ __forceinline__ void wave_lds_barrier() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t wg_sum(uint32_t v, uint32_t* s_red) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if (lane == 0) s_red[wave] = v;
+    lds_sync();
+    uint32_t t = 0;
+    for (uint32_t w = 0; w < blockDim.x / 64; ++w) t += s_red[w];
+    lds_sync();
+    return t;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ forward
+// One workgroup per block of m <= 16384 bytes.  A key is
+// (group value << 14) | position: first the rotation's first four bytes, then,
+// once ranks exist, (rank, rank of the rotation h bytes further) -- so the
+// sorted keys order the rotations by their first 4, 8, 16, ... bytes, with
+// ties in start position.  Each round gives every rotation the slot of the
+// first key of its group as its rank, stops when all ranks differ (or when
+// h >= m: rotations still tied are equal and stay in start order), and
+// otherwise forms the next keys and sorts again with h doubled.  Each thread
+// owns a contiguous run of sort slots (and of positions).
+__global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__ in, uint64_t n, uint32_t block,
+                                                     uint32_t every_log2, uint8_t* __restrict__ last,
+                                                     uint16_t* __restrict__ rows) {
+    __shared__ unsigned long long s_key[HUFF_BWT_MAX_BLOCK];
+    __shared__ uint8_t s_blk[HUFF_BWT_MAX_BLOCK];
+    __shared__ uint32_t s_red[kBwtThreads / 64];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t lo = (uint64_t)blockIdx.x * block;
+    const uint32_t m = (uint32_t)min<uint64_t>(block, n - lo);
+    uint32_t np = 2 * kBwtThreads;
+    while (np < m) np <<= 1;
+    const uint32_t per = np / kBwtThreads;
+    const uint32_t q0 = tid * per;
+
+    for (uint32_t i = tid; i < m; i += kBwtThreads) s_blk[i] = in[lo + i];
+    lds_sync();
+    for (uint32_t e = 0; e < per; ++e) {
+        const uint32_t i = q0 + e;
+        unsigned long long k = ~0ull;
+        if (i < m) {
+            const uint32_t c4 = (uint32_t)s_blk[i] << 24 | (uint32_t)s_blk[(i + 1) % m] << 16 |
+                                (uint32_t)s_blk[(i + 2) % m] << 8 | (uint32_t)s_blk[(i + 3) % m];
+            k = ((unsigned long long)c4 << kPosBits) | i;
+        }
+        s_key[i] = k;
+    }
+    lds_sync();
+    lds_bitonic_sort(s_key, np);
+
+    for (uint32_t h = 4;; h <<= 1) {
+        // heads of groups in this thread's slots, then the group open before them
+        unsigned long long prev = q0 ? s_key[q0 - 1] : 0ull;
+        uint32_t lasthead = 0, heads = 0;
+        for (uint32_t e = 0; e < per; ++e) {
+            const uint32_t q = q0 + e;
+            const unsigned long long k = s_key[q];
+            if (q < m && (q == 0 || (k >> kPosBits) != (prev >> kPosBits))) {
+                lasthead = q;
+                ++heads;
+            }
+            prev = k;
+        }
+        const uint32_t open = wg_excl_max(lasthead, s_red);
+        if (wg_sum(heads, s_red) == m || h >= m) break;
+        uint32_t rank[kMaxPer], pos[kMaxPer];
+        uint32_t run = open;
+        prev = q0 ? s_key[q0 - 1] : 0ull;
+#pragma unroll
+        for (uint32_t e = 0; e < kMaxPer; ++e) {
+            rank[e] = pos[e] = 0;
+            if (e < per) {
+                const uint32_t q = q0 + e;
+                const unsigned long long k = s_key[q];
+                if (q < m && (q == 0 || (k >> kPosBits) != (prev >> kPosBits))) run = q;
+                rank[e] = run;
+                pos[e] = (uint32_t)(k & kPosMask);
+                prev = k;
+            }
+        }
+        lds_sync();  // every sorted key has been read
+#pragma unroll
+        for (uint32_t e = 0; e < kMaxPer; ++e)
+            if (e < per && q0 + e < m) s_key[pos[e]] = rank[e];
+        lds_sync();
+        unsigned long long nk[kMaxPer];
+#pragma unroll
+        for (uint32_t e = 0; e < kMaxPer; ++e) {
+            const uint32_t i = q0 + e;
+            nk[e] = ~0ull;
+            if (e < per && i < m) {
+                const uint32_t j = i + h < m ? i + h : i + h - m;  // h < m here
+                nk[e] = (s_key[i] << (2 * kPosBits)) | (s_key[j] << kPosBits) | i;
+            }
+        }
+        lds_sync();
+#pragma unroll
+        for (uint32_t e = 0; e < kMaxPer; ++e)
+            if (e < per) s_key[q0 + e] = nk[e];
+        lds_sync();
+        lds_bitonic_sort(s_key, np);
+    }
+
+    // the last column, and the rows of the rotations starting at multiples of `every`
+    for (uint32_t q = tid; q < m; q += kBwtThreads) {
+        const uint32_t p = (uint32_t)(s_key[q] & kPosMask);
+        last[lo + q] = s_blk[p ? p - 1 : m - 1];
+        if ((p & ((1u << every_log2) - 1)) == 0) rows[(lo + p) >> every_log2] = (uint16_t)q;
+    }
+}
+
+// ------------------------------------------------------- move to front
+// One wave per block.  The list of the 256 byte values is spread over the
+// wave, four entries per lane: byte j of lane l is list position 4l + j.  A
+// lane reads 64 input bytes at a time; the wave then takes them in order,
+// each as a uniform value: the lane whose word holds the byte (a zero-byte
+// test of the word xor the byte) gives the position, and every entry before
+// that position moves one place back (each lane shifts its word up a byte
+// and takes the previous lane's top byte), the byte going to the front.
+template <bool kInverse>
+__global__ __launch_bounds__(256) void k_mtf(const uint8_t* __restrict__ in, uint64_t n, uint32_t block,
+                                             uint8_t* __restrict__ out) {
+    const uint32_t lane = threadIdx.x & 63;
+    const uint64_t b = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint64_t lo = b * block;
+    if (lo >= n) return;  // the whole wave
+    const uint32_t m = (uint32_t)min<uint64_t>(block, n - lo);
+    uint32_t w = (4 * lane) | (4 * lane + 1) << 8 | (4 * lane + 2) << 16 | (4 * lane + 3) << 24;
+    for (uint32_t base = 0; base < m; base += 64) {
+        const uint32_t cnt = min(64u, m - base);
+        const uint32_t v = lane < cnt ? in[lo + base + lane] : 0u;
+        uint32_t res = 0;
+        for (uint32_t t = 0; t < cnt; ++t) {
+            const uint32_t x = __builtin_amdgcn_readlane(v, t);
+            uint32_t at, j, c;
+            if constexpr (!kInverse) {
+                c = x;
+                const uint32_t d = w ^ (c * 0x01010101u);
+                const uint32_t z = (d - 0x01010101u) & ~d & 0x80808080u;  // lowest set bit: first zero byte
+                const uint64_t hit = __ballot(z != 0);
+                at = (uint32_t)__builtin_ctzll(hit);
+                j = (uint32_t)__builtin_ctz(__builtin_amdgcn_readlane(z, at)) >> 3;
+            } else {
+                at = x >> 2;
+                j = x & 3;
+                c = (__builtin_amdgcn_readlane(w, at) >> (8 * j)) & 0xffu;
+            }
+            // entries before position 4*at + j move back one place; c goes to the front
+            uint32_t up = __shfl_up(w >> 24, 1, 64);
+            if (lane == 0) up = c;
+            const uint32_t sh = (w << 8) | up;
+            const uint32_t keep = j == 3 ? 0u : 0xffffffffu << (8 * (j + 1));  // bytes after position j stay
+            if (lane < at) w = sh;
+            else if (lane == at) w = (w & keep) | (sh & ~keep);
+            if (lane == t) res = kInverse ? c : 4 * at + j;
+        }
+        if (lane < cnt) out[lo + base + lane] = (uint8_t)res;
+    }
+}
+
+// ------------------------------------------------------------ inverse
+// One workgroup per block.  The row that follows row r one position back in
+// the block is lf[r] = (bytes of the last column smaller than L[r]) + (copies
+// of L[r] before row r).  The second count is stable: each wave counts a
+// contiguous part of the rows, the parts' counts are summed in wave order,
+// and inside a part 64 rows at a time find the earlier equal bytes in their
+// group from eight ballots (one per bit).  Then walker w rebuilds bytes
+// [w*every, (w+1)*every) backwards from the recorded row of the rotation
+// that starts right after them.
+__global__ __launch_bounds__(kBwtThreads) void k_unbwt(const uint8_t* __restrict__ last, uint64_t n, uint32_t block,
+                                                       uint32_t every_log2, const uint16_t* __restrict__ rows,
+                                                       uint8_t* __restrict__ out, int32_t* status) {
+    constexpr uint32_t kWaves = kBwtThreads / 64;
+    __shared__ uint8_t s_L[HUFF_BWT_MAX_BLOCK];
+    __shared__ uint16_t s_lf[HUFF_BWT_MAX_BLOCK];
+    __shared__ uint8_t s_out[HUFF_BWT_MAX_BLOCK];
+    __shared__ uint32_t s_cnt[kWaves][256];  // per wave: copies of each byte in its part, then its base
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint64_t lo = (uint64_t)blockIdx.x * block;
+    const uint32_t m = (uint32_t)min<uint64_t>(block, n - lo);
+    for (uint32_t i = tid; i < m; i += kBwtThreads) s_L[i] = last[lo + i];
+    for (uint32_t i = tid; i < kWaves * 256; i += kBwtThreads) (&s_cnt[0][0])[i] = 0;
+    lds_sync();
+    // each wave's part: rows [p0, p1), whole groups of 64
+    const uint32_t span = ((m + kWaves - 1) / kWaves + 63) & ~63u;
+    const uint32_t p0 = min(m, wave * span), p1 = min(m, p0 + span);
+    for (uint32_t r = p0 + lane; r < p1; r += 64) atomicAdd(&s_cnt[wave][s_L[r]], 1u);
+    lds_sync();
+    __shared__ uint32_t s_tot[256], s_wtot[4];
+    if (tid < 256) {
+        // byte value tid: its copies in the earlier parts, and its total
+        uint32_t run = 0;
+        for (uint32_t w = 0; w < kWaves; ++w) {
+            const uint32_t c = s_cnt[w][tid];
+            s_cnt[w][tid] = run;
+            run += c;
+        }
+        s_tot[tid] = run;
+    }
+    lds_sync();
+    uint32_t x = 0;
+    if (tid < 256) {
+        // the copies of all smaller byte values: exclusive scan of the totals
+        x = s_tot[tid];
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t y = __shfl_up(x, d, 64);
+            if (lane >= (uint32_t)d) x += y;
+        }
+        if (lane == 63) s_wtot[wave] = x;
+    }
+    lds_sync();
+    if (tid < 256) {
+        uint32_t before = 0;
+        for (uint32_t w = 0; w < wave; ++w) before += s_wtot[w];
+        const uint32_t smaller = before + x - s_tot[tid];
+        for (uint32_t w = 0; w < kWaves; ++w) s_cnt[w][tid] += smaller;
+    }
+    lds_sync();
+    // stable ranks inside the part, 64 rows at a time
+    for (uint32_t r0 = p0; r0 < p1; r0 += 64) {
+        const uint32_t r = r0 + lane;
+        const bool on = r < p1;
+        const uint32_t c = on ? s_L[r] : 0u;
+        uint64_t eq = __ballot(on);
+        for (uint32_t bit = 0; bit < 8; ++bit) {
+            const uint64_t ones = __ballot(on && ((c >> bit) & 1));
+            eq &= ((c >> bit) & 1) ? ones : ~ones;
+        }
+        const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+        const uint32_t rank = (uint32_t)__popcll(eq & below);
+        if (on) s_lf[r] = (uint16_t)(s_cnt[wave][c] + rank);
+        wave_lds_barrier();
+        // the last copy of each byte value in the group moves its base on
+        if (on && (eq >> lane) == 1ull) s_cnt[wave][c] += (uint32_t)__popcll(eq);
+        wave_lds_barrier();
+    }
+    lds_sync();
+    // walkers
+    const uint32_t S = 1u << every_log2;
+    const uint32_t nwalk = (m + S - 1) >> every_log2;
+    for (uint32_t wk = tid; wk < nwalk; wk += kBwtThreads) {
+        const uint32_t beg = wk << every_log2, end = min(m, beg + S);
+        uint32_t r = rows[(lo + (end == m ? 0 : end)) >> every_log2];
+        if (r >= m) {
+            atomicMin(status, (int32_t)HUFF_E_CORRUPT);
+            continue;
+        }
+        for (uint32_t p = end; p-- > beg;) {
+            s_out[p] = s_L[r];
+            r = s_lf[r];
+        }
+    }
+    lds_sync();
+    for (uint32_t i = tid; i < m; i += kBwtThreads) out[lo + i] = s_out[i];
+}
+
+hipError_t launch_bwt(const uint8_t* in, uint64_t n, uint32_t block, uint32_t every_log2, uint8_t* last,
+                      uint16_t* rows, hipStream_t s) {
+    const uint64_t nblk = (n + block - 1) / block;
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bwt, dim3((uint32_t)nblk), dim3(kBwtThreads), 0, s, in, n, block, every_log2, last, rows);
+    return hipGetLastError();
+}
+
+hipError_t launch_unbwt(const uint8_t* last, uint64_t n, uint32_t block, uint32_t every_log2, const uint16_t* rows,
+                        uint8_t* out, int32_t* status, hipStream_t s) {
+    const uint64_t nblk = (n + block - 1) / block;
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_unbwt, dim3((uint32_t)nblk), dim3(kBwtThreads), 0, s, last, n, block, every_log2, rows, out,
+                       status);
+    return hipGetLastError();
+}
+
+hipError_t launch_mtf(const uint8_t* in, uint64_t n, uint32_t block, uint8_t* out, bool inverse, hipStream_t s) {
+    const uint64_t nblk = (n + block - 1) / block;
+    if (nblk == 0) return hipSuccess;
+    const dim3 grid((uint32_t)((nblk + 3) / 4)), wg(256);
+    if (inverse) hipLaunchKernelGGL(k_mtf<true>, grid, wg, 0, s, in, n, block, out);
+    else hipLaunchKernelGGL(k_mtf<false>, grid, wg, 0, s, in, n, block, out);
+    return hipGetLastError();
+}
+
+}  // namespace huff

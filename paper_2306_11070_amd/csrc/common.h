@@ -166,5 +166,11 @@ hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, uint32_t bloc
 hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
 hipError_t launch_compare(const CmpJob* jobs, uint32_t njobs, uint64_t total_bytes, hipStream_t s);
+// Method 3's block transform (bwt.hip).
+hipError_t launch_bwt(const uint8_t* in, uint64_t n, uint32_t block, uint32_t every_log2, uint8_t* last,
+                      uint16_t* rows, hipStream_t s);
+hipError_t launch_unbwt(const uint8_t* last, uint64_t n, uint32_t block, uint32_t every_log2, const uint16_t* rows,
+                        uint8_t* out, int32_t* status, hipStream_t s);
+hipError_t launch_mtf(const uint8_t* in, uint64_t n, uint32_t block, uint8_t* out, bool inverse, hipStream_t s);
 
 }  // namespace huff
