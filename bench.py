@@ -442,6 +442,88 @@ def segments_leg(P, codec, x, T_global: int, seg: int, sub: int, reps: int):
             "graph": True, "roundtrip_ok": ok}
 
 
+def method3_leg(P, params: dict, workload: str, block: int, every: int, chunk: int, sub: int, steps: int,
+                flush: Flusher, check: bool):
+    """Method 3 (block transform + move-to-front + Huffman code) on one
+    workload: per-phase HIP-event times (flushed), size against the plain
+    Huffman code, and (check) every output against the oracle."""
+    import numpy as np
+    import torch
+
+    import datagen
+
+    codec = P.Codec(0, params)
+    a = datagen.workload(workload)
+    n = a.size
+    x = torch.from_numpy(a).cuda()
+    dev = x.device
+    o = dict(last=torch.empty(n, dtype=torch.uint8, device=dev),
+             rows=torch.empty(max(1, (n + every - 1) // every), dtype=torch.int16, device=dev),
+             mtf=torch.empty(n, dtype=torch.uint8, device=dev),
+             hist=torch.empty(256, dtype=torch.int64, device=dev),
+             dcb=torch.empty(P.DCB_BYTES, dtype=torch.uint8, device=dev),
+             words=torch.empty((n + 3) // 4 + 4, dtype=torch.int32, device=dev),
+             chunk_off=torch.empty((n + chunk - 1) // chunk + 1, dtype=torch.int64, device=dev),
+             sub_lo=torch.empty((n + sub - 1) // sub + 1, dtype=torch.int32, device=dev))
+    w = dict(mtf=torch.empty(n, dtype=torch.uint8, device=dev), last=torch.empty(n, dtype=torch.uint8, device=dev))
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    st = torch.zeros(1, dtype=torch.int32, device=dev)
+    names = ("bwt", "mtf", "huffman_compress", "huffman_decode", "unmtf", "unbwt")
+    times = {k: [] for k in names}
+    for it in range(steps + 2):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        flush()
+        ev[0].record()
+        codec.bwt(x, block, every, last=o["last"], rows=o["rows"])
+        ev[1].record()
+        codec.mtf(o["last"], block, out=o["mtf"])
+        ev[2].record()
+        c = codec.compress(o["mtf"], chunk, sub, status=st, out=o)
+        ev[3].record()
+        codec.decompress(c, out=w["mtf"], status=st)
+        ev[4].record()
+        codec.unmtf(w["mtf"], block, out=w["last"])
+        ev[5].record()
+        codec.unbwt(w["last"], block, every, o["rows"], out=out, status=st)
+        ev[6].record()
+        torch.cuda.synchronize()
+        if it >= 2:
+            for i, k in enumerate(names):
+                times[k].append(ev[i].elapsed_time(ev[i + 1]))
+    ok = int(st.item()) == 0 and bool(torch.equal(out, x))
+    T3 = int(c["chunk_off"][-1].item())
+    plain = codec.compress(x, chunk, sub)
+    T1 = int(plain["chunk_off"][-1].item())
+    ms = {k: float(np.mean(v)) for k, v in times.items()}
+    comp_ms = ms["bwt"] + ms["mtf"] + ms["huffman_compress"]
+    dec_ms = ms["huffman_decode"] + ms["unmtf"] + ms["unbwt"]
+    res = {"workload": f"{workload}, blocks of {block} bytes, a row every {every} bytes, chunks of {chunk}, "
+                       f"decode index every {sub} bytes",
+           "n_bytes": n, "phase_ms": {k: round(v, 4) for k, v in ms.items()},
+           "phase_GBps": {k: round(n / (v * 1e-3) / 1e9, 2) for k, v in ms.items()},
+           "compress_GBps": round(n / (comp_ms * 1e-3) / 1e9, 2), "decode_GBps": round(n / (dec_ms * 1e-3) / 1e9, 2),
+           "GBps": round(n / ((comp_ms + dec_ms) * 1e-3) / 1e9, 2),
+           "bits_per_byte": round(T3 / n, 4), "plain_huffman_bits_per_byte": round(T1 / n, 4),
+           "size_vs_plain_huffman": round((T3 / 8 + 2 * ((n + every - 1) // every)) / (T1 / 8), 4),
+           "bound": "alu", "roundtrip_ok": ok}
+    if check:
+        import oracle
+        t0 = time.perf_counter()
+        r = oracle.compress_bwt(a, block, every, chunk, sub)
+        t1 = time.perf_counter()
+        nw = r["words"].size
+        res["bitexact_vs_oracle"] = bool(
+            np.array_equal(o["last"].cpu().numpy(), r["last"])
+            and np.array_equal(o["rows"].cpu().numpy().view(np.uint16).astype(np.uint32), r["rows"])
+            and np.array_equal(o["words"][:nw].cpu().numpy().view(np.uint32), r["words"])
+            and np.array_equal(o["chunk_off"].cpu().numpy().view(np.uint64), r["chunk_off"]))
+        res["cpu_baseline"] = {"value": round(n / (t1 - t0) / 1e9, 5), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole {n}-byte workload, transform + move-to-front + Huffman compress "
+                                         f"(plain serial C, one thread)"}
+    codec.close()
+    return res
+
+
 def serve_leg(P, params: dict, seconds: float, pool_n: int, loads, chunk: int, sub: int):
     """Open-loop serving: Poisson arrivals at fractions of the saturation
     rate, 70 % compress / 30 % decompress of resident streams, request sizes
@@ -561,6 +643,7 @@ def main():
     ap.add_argument("--segment", type=int, default=256 << 10, help="segment bytes of the per-segment codebook leg")
     ap.add_argument("--sweep", action="store_true",
                     help="also time compress and decode over chunk sizes 16 KiB-4 MiB, with and without the sub-block index")
+    ap.add_argument("--no-method3", action="store_true", help="skip the block transform (Method 3) leg")
     ap.add_argument("--serve-seconds", type=float, default=10.0)
     ap.add_argument("--serve-pool", type=int, default=384)
     args = ap.parse_args()
@@ -664,6 +747,10 @@ def main():
         del r2, x2
         torch.cuda.empty_cache()
     codec.close()
+    if not args.no_method3:
+        line["method3"] = [method3_leg(P, params, wl, 16384, 256, 256 << 10, 128, 5, flush, not args.no_cpu)
+                           for wl in ("words_45MiB", "markov_45MiB")]
+        torch.cuda.empty_cache()
     if not args.no_batch:
         line["batch"] = batch_leg(P, params, args.batch_files, 10, 256 << 10, sub)
         torch.cuda.empty_cache()

@@ -105,7 +105,10 @@ typedef struct huff_dcb {
     uint16_t lut[1 << HUFF_LUT_BITS]; /* peek lut_bits bits -> sym | len << 8; 0 = longer code */
 } huff_dcb;
 
-/* Launch knobs; 0 selects the built-in or autotuned default. */
+/* Launch knobs (they change how the work is split, never the output).  A
+   field of 0 keeps the library's built-in default for it; the autotuner
+   (paper_2306_11070_amd/autotune.py) times candidates on the caller's data
+   and passes its choices in through these fields. */
 typedef struct huff_params {
     uint32_t hist_blocks;     /* histogram workgroups (persistent grid) */
     uint32_t hist_depth;      /* histogram replicas per workgroup (1..32, power of 2) */
@@ -240,8 +243,10 @@ huff_status huff_decode(huff_ctx* ctx, const uint32_t* d_words, uint64_t nwords,
                         const huff_dcb* d_cb, uint8_t* d_out, int32_t* d_status, void* stream);
 
 /*
- * Plain device copy of `bytes` bytes with 16-byte vector loads and stores:
- * the bandwidth probe the kernels are compared against.
+ * Plain device copy of `bytes` bytes (the bandwidth probe the kernels are
+ * compared against): a persistent grid of eight workgroups per compute unit,
+ * each thread keeping eight 16-byte non-temporal loads in flight before it
+ * stores them.  d_src and d_dst must be 16-byte aligned.
  */
 huff_status huff_copy(huff_ctx* ctx, const void* d_src, void* d_dst, uint64_t bytes, void* stream);
 

@@ -229,9 +229,11 @@ __global__ __launch_bounds__(256) void k_mtf(const uint8_t* __restrict__ in, uin
                 j = x & 3;
                 c = (__builtin_amdgcn_readlane(w, at) >> (8 * j)) & 0xffu;
             }
-            // entries before position 4*at + j move back one place; c goes to the front
-            uint32_t up = __shfl_up(w >> 24, 1, 64);
-            if (lane == 0) up = c;
+            // entries before position 4*at + j move back one place; c goes to
+            // the front.  The previous lane's top byte comes by a DPP shift of
+            // the whole wave by one lane (no LDS round trip); lane 0 takes c.
+            uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp((int)c, (int)(w >> 24), 0x138 /* wave_shr:1 */, 0xf,
+                                                                0xf, false);
             const uint32_t sh = (w << 8) | up;
             const uint32_t keep = j == 3 ? 0u : 0xffffffffu << (8 * (j + 1));  // bytes after position j stay
             if (lane < at) w = sh;
