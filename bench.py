@@ -44,7 +44,7 @@ REFUSED = {"markov_2GiB", "zipf256_2GiB"}
 # otherwise.
 KERNEL_NAMES = {"hist": "k_hist", "codebook": "k_codebook", "scan": "k_tile_scan", "encode": "k_encode",
                 "decode": "k_decode_lds"}
-TUNE_SPACE = {"hist_depth": [8, 16, 32], "hist_blocks_per_cu": [2, 4], "enc_blocks_per_cu": [2, 3, 4],
+TUNE_SPACE = {"hist_depth": [8, 16, 32], "hist_blocks_per_cu": [4, 16], "enc_blocks_per_cu": [4, 16, 256],
               "sub_size": [64, 128, 256], "dec_block": [256]}
 
 

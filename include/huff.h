@@ -113,7 +113,8 @@ typedef struct huff_params {
     uint32_t hist_blocks;     /* histogram workgroups (persistent grid) */
     uint32_t hist_depth;      /* histogram replicas per workgroup (1..32, power of 2) */
     uint32_t dec_block;       /* direct-decode workgroup size (64, 128, 192 or 256) */
-    uint32_t enc_blocks_per_cu; /* persistent encode workgroups per compute unit (1..16) */
+    uint32_t enc_blocks_per_cu; /* encode workgroups per compute unit (1..1024; a grid of at least one
+                                   workgroup per 16 KiB tile takes one tile per workgroup) */
 } huff_params;
 
 typedef struct huff_ctx huff_ctx;
@@ -244,9 +245,9 @@ huff_status huff_decode(huff_ctx* ctx, const uint32_t* d_words, uint64_t nwords,
 
 /*
  * Plain device copy of `bytes` bytes (the bandwidth probe the kernels are
- * compared against): a persistent grid of eight workgroups per compute unit,
- * each thread keeping eight 16-byte non-temporal loads in flight before it
- * stores them.  d_src and d_dst must be 16-byte aligned.
+ * compared against): one workgroup per contiguous 16 KiB, each thread
+ * issuing four 16-byte non-temporal loads before it stores them.  d_src and
+ * d_dst must be 16-byte aligned.
  */
 huff_status huff_copy(huff_ctx* ctx, const void* d_src, void* d_dst, uint64_t bytes, void* stream);
 

@@ -24,8 +24,8 @@ import time
 
 DEFAULT_SPACE = {
     "hist_depth": [1, 2, 4, 8, 16, 32],
-    "hist_blocks_per_cu": [1, 2, 4],
-    "enc_blocks_per_cu": [1, 2, 3, 4],
+    "hist_blocks_per_cu": [2, 4, 8, 16],
+    "enc_blocks_per_cu": [2, 4, 16, 64, 256],
     "sub_size": [0, 32, 64, 128, 256, 512],
     "dec_block": [64, 128, 256],
     "chunk_size": [16 << 10, 32 << 10, 64 << 10, 128 << 10, 256 << 10, 512 << 10, 1 << 20, 2 << 20, 4 << 20],

@@ -162,7 +162,7 @@ hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo, hipStream_t s);
 // out_aligned: every output is 16-byte aligned (the staged decoder requires it)
 hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hipStream_t s);
-hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, uint32_t blocks, hipStream_t s);
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
 hipError_t launch_compare(const CmpJob* jobs, uint32_t njobs, uint64_t total_bytes, hipStream_t s);

@@ -1932,35 +1932,40 @@ hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t
     return hipGetLastError();
 }
 
-// The bandwidth probe: a persistent grid copies 16-byte vectors, each
-// thread keeping kCopyInFlight loads in flight before it stores them, with
-// non-temporal loads and stores (the probe's data is never reused).  The
-// bytes past the last whole vector are copied by the first workgroup.
-constexpr int kCopyInFlight = 8;
+// The bandwidth probe: workgroup b copies the contiguous vectors
+// [b * kCopyChunk, (b + 1) * kCopyChunk) of 16 bytes, each thread issuing
+// its kCopyInFlight non-temporal loads before it stores them (the probe's
+// data is never reused).  Of the variants measured on MI355X (persistent
+// grids of 512-65536 workgroups with 1-8 loads in flight, contiguous chunks
+// of 16-128 KiB per workgroup), one 16 KiB chunk per workgroup moved the
+// most.  The bytes past the last whole vector are copied by the first
+// workgroup.
+constexpr int kCopyInFlight = 4;
+constexpr uint64_t kCopyChunk = 256 * kCopyInFlight;  // vectors per workgroup
 typedef uint32_t v4u32_t __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void k_copy(const uint8_t* __restrict__ src, uint8_t* __restrict__ dst, uint64_t bytes) {
     const uint64_t nvec = bytes >> 4;
     const v4u32_t* s = reinterpret_cast<const v4u32_t*>(src);
     v4u32_t* d = reinterpret_cast<v4u32_t*>(dst);
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i + (kCopyInFlight - 1) * stride < nvec; i += kCopyInFlight * stride) {
-        v4u32_t v[kCopyInFlight];
+    const uint64_t b0 = (uint64_t)blockIdx.x * kCopyChunk + threadIdx.x;
+    v4u32_t v[kCopyInFlight];
 #pragma unroll
-        for (int k = 0; k < kCopyInFlight; ++k) v[k] = __builtin_nontemporal_load(s + i + k * stride);
-#pragma unroll
-        for (int k = 0; k < kCopyInFlight; ++k) __builtin_nontemporal_store(v[k], d + i + k * stride);
+    for (int k = 0; k < kCopyInFlight; ++k) {
+        const uint64_t i = b0 + 256 * k;
+        v[k] = i < nvec ? __builtin_nontemporal_load(s + i) : v4u32_t{0, 0, 0, 0};
     }
-    for (; i < nvec; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(s + i), d + i);
+#pragma unroll
+    for (int k = 0; k < kCopyInFlight; ++k) {
+        const uint64_t i = b0 + 256 * k;
+        if (i < nvec) __builtin_nontemporal_store(v[k], d + i);
+    }
     if (blockIdx.x == 0)
         for (uint64_t b = (nvec << 4) + threadIdx.x; b < bytes; b += blockDim.x) dst[b] = src[b];
 }
 
-hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, uint32_t blocks, hipStream_t s) {
-    const uint64_t need = (bytes / 16 + 255) / 256;
-    uint64_t g = blocks ? blocks : 2048;
-    if (g > need) g = need;
+hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s) {
+    uint64_t g = ((bytes >> 4) + kCopyChunk - 1) / kCopyChunk;
     if (g == 0) g = 1;
     hipLaunchKernelGGL(k_copy, dim3((uint32_t)g), dim3(256), 0, s, (const uint8_t*)src, (uint8_t*)dst, bytes);
     return hipGetLastError();
