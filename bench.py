@@ -132,9 +132,10 @@ class Flusher:
             self.buf.fill_(self.k)
 
 
-def run_stream(P, codec, x, chunk: int, sub: int, steps: int, warmup: int, flush: Flusher):
-    """Times `steps` flushed steps (compress + decode) with HIP events, then the
-    same steps again with the library's per-kernel event timing."""
+def run_stream(P, codec, x, chunk: int, sub: int, steps: int, warmup: int, flush: Flusher, graph: bool = False):
+    """Times `steps` flushed steps (compress + decode, each replayed from a HIP
+    graph when `graph`) with HIP events, then the same steps again, eagerly,
+    with the library's per-kernel event timing."""
     import numpy as np
     import torch
 
@@ -148,25 +149,47 @@ def run_stream(P, codec, x, chunk: int, sub: int, steps: int, warmup: int, flush
     out = torch.empty(n, dtype=torch.uint8, device=dev)
     status = torch.zeros(1, dtype=torch.int32, device=dev)
 
-    def step(ev=None):
+    def compress():
+        codec.compress(x, chunk, sub, status=status, out=bufs)
+
+    def decode():
+        codec.decode(bufs["words"], bufs["words"].numel(), bufs["chunk_off"], n, chunk, bufs["dcb"],
+                     bufs["sub_lo"], sub, out=out, status=status)
+
+    def step(ev=None, run_c=compress, run_d=decode):
         flush()
         if ev is not None:
             ev[0].record()
-        codec.compress(x, chunk, sub, status=status, out=bufs)
+        run_c()
         if ev is not None:
             ev[1].record()
-        codec.decode(bufs["words"], bufs["words"].numel(), bufs["chunk_off"], n, chunk, bufs["dcb"],
-                     bufs["sub_lo"], sub, out=out, status=status)
+        run_d()
         if ev is not None:
             ev[2].record()
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    run_c, run_d = compress, decode
+    if graph:
+        # each call's launches captured once into a HIP graph and replayed
+        # (the context's workspaces are sized by the eager warm-up steps)
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        gc, gd = torch.cuda.CUDAGraph(), torch.cuda.CUDAGraph()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(gc, stream=s):
+                compress()
+            with torch.cuda.graph(gd, stream=s):
+                decode()
+        torch.cuda.synchronize()
+        run_c, run_d = gc.replay, gd.replay
+        step(None, run_c, run_d)
+        torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     t0 = time.perf_counter()
     for k in range(steps):
-        step(evs[k])
+        step(evs[k], run_c, run_d)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     comp = [evs[k][0].elapsed_time(evs[k][1]) for k in range(steps)]
@@ -176,7 +199,7 @@ def run_stream(P, codec, x, chunk: int, sub: int, steps: int, warmup: int, flush
     # out of the pass above: each event pair adds a few us between launches)
     codec.set_timing(True)
     for _ in range(steps):
-        step()
+        step(None, compress, decode)
     torch.cuda.synchronize()
     ktime = {k: codec.kernel_time(k) for k in KERNEL_NAMES}
     codec.set_timing(False)
@@ -632,6 +655,8 @@ def main():
     ap.add_argument("--sub", type=int, default=None, help="decode sub-block bytes (0: chunk index only)")
     ap.add_argument("--flush-mib", type=int, default=512, help="MiB written between steps (0: none)")
     ap.add_argument("--no-tune", action="store_true", help="fixed default launch parameters, no autotuning")
+    ap.add_argument("--graph", action="store_true",
+                    help="time each call's launches replayed from a HIP graph (measured slower than eager calls)")
     ap.add_argument("--tune-cache", default=os.path.join(ROOT, "gpurun_out", "autotune.json"))
     ap.add_argument("--cpu-sample-mib", type=int, default=256, help="oracle baseline on the leading MiB")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle legs (profiling runs)")
@@ -684,7 +709,7 @@ def main():
     if args.sub is not None:
         sub = args.sub
     codec = P.Codec(0, params)
-    r = run_stream(P, codec, x, chunk, sub, args.steps, args.warmup, flush)
+    r = run_stream(P, codec, x, chunk, sub, args.steps, args.warmup, flush, graph=args.graph)
     rep = stream_report(P, n, chunk, sub, r, args.workload)
     cp = copy_probe(codec, x, r["out"], flush)
     value = n / (rep["step_ms"] * 1e-3) / 1e9
@@ -707,6 +732,7 @@ def main():
                    "max_code_len": rep["max_len"], "index_bytes": rep["index_bytes"],
                    "stream_over_input": round((rep["T"] / 8 + rep["index_bytes"]) / n, 4),
                    "cache": f"{args.flush_mib} MiB written between steps (not timed)",
+                   "launch": "each call's launches replayed from a HIP graph" if args.graph else "eager calls",
                    "step": "huff_compress (histogram + device codebook + encode) + huff_decode"},
         "wall_s_timed_steps_incl_flush": round(r["wall_s"], 4),
         "phases": rep["phases"],
@@ -735,7 +761,7 @@ def main():
         d2, c2, s2 = WORKLOADS["markov_45MiB"]
         a2 = datagen.workload("markov_45MiB")
         x2 = torch.from_numpy(a2).to(dev)
-        r2 = run_stream(P, codec, x2, c2, s2, 20, 5, flush)
+        r2 = run_stream(P, codec, x2, c2, s2, 20, 5, flush, graph=args.graph)
         rep2 = stream_report(P, a2.size, c2, s2, r2, "markov_45MiB")
         ps = {"workload": f"markov_45MiB: {d2}, chunks of {c2} bytes, decode index every {s2} bytes",
               "value_GBps": round(a2.size / (rep2["step_ms"] * 1e-3) / 1e9, 2), "ms_per_step": round(rep2["step_ms"], 4),

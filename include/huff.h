@@ -42,6 +42,12 @@
  *   - A context owns small device workspaces that its kernels update in
  *     place; calls that share one context must be ordered (one stream at a
  *     time).  Use one context per concurrent stream.
+ *   - The device calls allocate nothing once the context's workspaces are
+ *     large enough for the input, so they can be captured into a HIP graph
+ *     after one eager call of the same size; a later call on that context
+ *     with a larger input grows (reallocates) the workspaces the graph
+ *     refers to.  Keep captured work on a context of its own, or use
+ *     huff_compress_noalloc.
  *   - Limits: n < 2^38 bytes per stream or file; chunk_size a power of two in
  *     [1 KiB, 64 MiB]; sub_size 0 (no sub index) or a power of two in
  *     [16, chunk_size].  Every byte present gets a code of at most 63 bits
