@@ -1724,16 +1724,24 @@ enum : int { kDecFits = 0, kDecLong = 1, kDecBoth = 2 };
 // last sub-block of a stream is decoded byte by byte.  Longer codes: each
 // lane decodes with a refilled window and stores 64 bytes at a time; codes
 // longer than 32 bits are decoded straight from memory.
+template <int S>
+struct StagedLds {
+    uint32_t in[4][64 * S / 4 + 8];
+    DecTables t;
+};
+
+// One block of 256 decode lanes (`blk`); every return below is either taken
+// by the whole workgroup or comes after the workgroup's last barrier.
 template <int S, bool kBatch, int kMode>
-__global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
+__device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk, StagedLds<S>& sm) {
     constexpr uint32_t kInWords = 64 * S / 4 + 8;
     constexpr uint32_t G = S / 16;
     constexpr int kLine = S < kDecLine ? S : kDecLine;
-    __shared__ uint32_t s_in[4][kInWords];
-    __shared__ DecTables t;
+    auto& s_in = sm.in;
+    DecTables& t = sm.t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     FileDesc f;
-    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, (uint64_t)blockIdx.x * 256)];
+    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, blk * 256)];
     else f = a.one;
     const huff_dcb* cb = f.cb;
     const uint32_t lutBits = cb->lut_bits, maxLen = cb->max_len;
@@ -1747,7 +1755,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
 
     const uint64_t n = f.n;
     const uint64_t nitems = (n + S - 1) / S;
-    const uint64_t j0 = (uint64_t)blockIdx.x * 256 + wave * 64 - f.first;  // first item of this wave
+    const uint64_t j0 = blk * 256 + wave * 64 - f.first;  // first item of this wave
     const uint64_t j = j0 + lane;
     const bool active = j < nitems;
     uint64_t start = 0, end = 0;
@@ -1887,19 +1895,49 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
     if (bad) report(f.status, a.err, HUFF_E_CORRUPT);
 }
 
-// Staged decode launches for one sub-block size.
+// One workgroup per block of 256 lanes.
+template <int S, bool kBatch, int kMode>
+__global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
+    __shared__ StagedLds<S> sm;
+    dec_staged_block<S, kBatch, kMode>(a, blockIdx.x, sm);
+}
+
+// The longer-code launch of one stream below 128 bytes: workgroup b takes blocks b,
+// b + grid, ...  (kept apart from k_decode_lds: the loop costs the
+// table-only path registers, about 64 -> 107 VGPRs at 64 bytes).
+template <int S, bool kBatch>
+__global__ __launch_bounds__(256) void k_decode_lds_long(DecArgs a) {
+    __shared__ StagedLds<S> sm;
+    const uint64_t nblk = (a.nitems + 255) / 256;
+    for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        dec_staged_block<S, kBatch, kDecLong>(a, blk, sm);
+        __syncthreads();  // the block's tables and buffers are free for the next
+    }
+}
+
+// Staged decode launches for one sub-block size.  Below 128 bytes the codes
+// that fit the peek table and the longer ones are two launches.  For one
+// stream, every block of the second launch exits at once unless the whole
+// stream has long codes, so it runs a small grid that loops over the blocks
+// (a full grid of workgroups that only exit costs ~16 us at 1 GiB); a batch
+// mixes codebooks and keeps one workgroup per block in both.
+constexpr uint32_t kDecSecondGrid = 1024;
+
 template <int SZ>
 hipError_t launch_staged(const DecArgs& a, hipStream_t s) {
-    const dim3 grid((uint32_t)((a.nitems + 255) / 256)), block(256);
+    const uint64_t nblk = (a.nitems + 255) / 256;
+    const dim3 grid((uint32_t)nblk), block(256);
+    const dim3 grid2((uint32_t)(nblk < kDecSecondGrid ? nblk : kDecSecondGrid));
     if constexpr (SZ >= 128) {
         if (a.files) hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecBoth>), grid, block, 0, s, a);
         else hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecBoth>), grid, block, 0, s, a);
     } else if (a.files) {
+        // a batch mixes codebooks: both launches have work, one block each
         hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecFits>), grid, block, 0, s, a);
         hipLaunchKernelGGL((k_decode_lds<SZ, true, kDecLong>), grid, block, 0, s, a);
     } else {
         hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecFits>), grid, block, 0, s, a);
-        hipLaunchKernelGGL((k_decode_lds<SZ, false, kDecLong>), grid, block, 0, s, a);
+        hipLaunchKernelGGL((k_decode_lds_long<SZ, false>), grid2, block, 0, s, a);
     }
     return hipGetLastError();
 }
