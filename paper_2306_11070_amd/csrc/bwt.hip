@@ -24,30 +24,102 @@ constexpr uint64_t kPosMask = (1u << kPosBits) - 1;
 constexpr uint32_t kMaxPer = HUFF_BWT_MAX_BLOCK / kBwtThreads;  // sort slots per thread
 static_assert(HUFF_BWT_MAX_BLOCK == 1u << kPosBits, "block positions fit kPosBits");
 
+// LDS slot of sort entry i: one spare slot after every 16, so that the 64
+// lanes of a wave reading runs of up to 16 consecutive 8-byte entries (one
+// run per lane) spread over the LDS banks instead of meeting in a few.
+__device__ __forceinline__ uint32_t kslot(uint32_t i) { return i + (i >> 4); }
+constexpr uint32_t kKeySlots = HUFF_BWT_MAX_BLOCK + HUFF_BWT_MAX_BLOCK / 16;
+
 __device__ __forceinline__ void lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Ascending bitonic sort of key[0..np) in LDS (np a power of two, at least
-// twice the workgroup size); every thread of the workgroup takes part.
-template <typename K>
-__device__ void lds_bitonic_sort(K* key, uint32_t np) {
-    const uint32_t tid = threadIdx.x, nt = blockDim.x;
-    for (uint32_t k = 2; k <= np; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t p = tid; p < np / 2; p += nt) {
-                const uint32_t i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
-                const uint32_t l = i | j;
-                const K a = key[i], b = key[l];
-                if ((a > b) == ((i & k) == 0)) {
-                    key[i] = b;
-                    key[l] = a;
+// Stages j = jtop, jtop/2, ..., 1 (all below E) of bitonic merge k on the
+// run r[0..E) of sort entries q0 .. q0+E-1 held in registers.
+template <uint32_t E, typename K>
+__device__ __forceinline__ void reg_merge(K (&r)[E], uint32_t q0, uint32_t k, uint32_t jtop) {
+#pragma unroll
+    for (uint32_t j = E / 2; j >= 1; j >>= 1) {
+        if (j <= jtop) {
+#pragma unroll
+            for (uint32_t e = 0; e < E; ++e) {
+                if ((e & j) == 0) {
+                    const bool up = ((q0 + e) & k) == 0;
+                    const K x = r[e], y = r[e | j];
+                    const K lo = x < y ? x : y, hi = x < y ? y : x;
+                    r[e] = up ? lo : hi;
+                    r[e | j] = up ? hi : lo;
                 }
+            }
+        }
+    }
+}
+
+// Ascending bitonic sort of key[0..np) in LDS (entry i at kslot(i)) by the
+// whole workgroup of kBwtThreads threads, np = E * kBwtThreads.  Thread t
+// owns entries [t*E, t*E + E).  The merges of runs up to E long happen in
+// registers, in one pass.  In every later merge, the stages whose pairs lie
+// E or more entries apart exchange through LDS -- every thread issues the
+// loads of all its E/2 pairs before it compares and stores them, so a stage
+// costs one LDS round trip -- and the stages with pairs closer than E that
+// close the merge run in registers with no barrier between them.
+template <uint32_t E, typename K>
+__device__ void lds_bitonic_sort_e(K* key) {
+    constexpr uint32_t np = E * kBwtThreads;
+    const uint32_t tid = threadIdx.x;
+    const uint32_t q0 = tid * E;
+    {
+        K r[E];
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) r[e] = key[kslot(q0 + e)];
+#pragma unroll
+        for (uint32_t k = 2; k <= E; k <<= 1) reg_merge<E>(r, q0, k, k >> 1);
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) key[kslot(q0 + e)] = r[e];
+    }
+    lds_sync();
+    for (uint32_t k = 2 * E; k <= np; k <<= 1) {
+        for (uint32_t j = k >> 1; j >= E; j >>= 1) {
+            K a[E / 2], b[E / 2];
+            uint32_t ii[E / 2];
+#pragma unroll
+            for (uint32_t e = 0; e < E / 2; ++e) {
+                const uint32_t p = tid + kBwtThreads * e;
+                const uint32_t i = ((p & ~(j - 1)) << 1) | (p & (j - 1));
+                ii[e] = i;
+                a[e] = key[kslot(i)];
+                b[e] = key[kslot(i | j)];
+            }
+#pragma unroll
+            for (uint32_t e = 0; e < E / 2; ++e) {
+                const uint32_t i = ii[e];
+                const bool up = (i & k) == 0;
+                const K lo = a[e] < b[e] ? a[e] : b[e], hi = a[e] < b[e] ? b[e] : a[e];
+                key[kslot(i)] = up ? lo : hi;
+                key[kslot(i | j)] = up ? hi : lo;
             }
             lds_sync();
         }
+        K r[E];
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) r[e] = key[kslot(q0 + e)];
+        reg_merge<E>(r, q0, k, E >> 1);
+#pragma unroll
+        for (uint32_t e = 0; e < E; ++e) key[kslot(q0 + e)] = r[e];
+        lds_sync();
+    }
+}
+
+// The sort for np = 2048, 4096, 8192 or 16384 entries.
+template <typename K>
+__device__ void lds_bitonic_sort_reg(K* key, uint32_t np) {
+    switch (np / kBwtThreads) {
+        case 2: lds_bitonic_sort_e<2>(key); break;
+        case 4: lds_bitonic_sort_e<4>(key); break;
+        case 8: lds_bitonic_sort_e<8>(key); break;
+        default: lds_bitonic_sort_e<16>(key); break;
     }
 }
 
@@ -106,7 +178,7 @@ __device__ __forceinline__ uint32_t wg_sum(uint32_t v, uint32_t* s_red) {
 __global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__ in, uint64_t n, uint32_t block,
                                                      uint32_t every_log2, uint8_t* __restrict__ last,
                                                      uint16_t* __restrict__ rows) {
-    __shared__ unsigned long long s_key[HUFF_BWT_MAX_BLOCK];
+    __shared__ unsigned long long s_key[kKeySlots];
     __shared__ uint8_t s_blk[HUFF_BWT_MAX_BLOCK];
     __shared__ uint32_t s_red[kBwtThreads / 64];
     const uint32_t tid = threadIdx.x;
@@ -127,18 +199,18 @@ __global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__
                                 (uint32_t)s_blk[(i + 2) % m] << 8 | (uint32_t)s_blk[(i + 3) % m];
             k = ((unsigned long long)c4 << kPosBits) | i;
         }
-        s_key[i] = k;
+        s_key[kslot(i)] = k;
     }
     lds_sync();
-    lds_bitonic_sort(s_key, np);
+    lds_bitonic_sort_reg(s_key, np);
 
     for (uint32_t h = 4;; h <<= 1) {
         // heads of groups in this thread's slots, then the group open before them
-        unsigned long long prev = q0 ? s_key[q0 - 1] : 0ull;
+        unsigned long long prev = q0 ? s_key[kslot(q0 - 1)] : 0ull;
         uint32_t lasthead = 0, heads = 0;
         for (uint32_t e = 0; e < per; ++e) {
             const uint32_t q = q0 + e;
-            const unsigned long long k = s_key[q];
+            const unsigned long long k = s_key[kslot(q)];
             if (q < m && (q == 0 || (k >> kPosBits) != (prev >> kPosBits))) {
                 lasthead = q;
                 ++heads;
@@ -149,13 +221,13 @@ __global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__
         if (wg_sum(heads, s_red) == m || h >= m) break;
         uint32_t rank[kMaxPer], pos[kMaxPer];
         uint32_t run = open;
-        prev = q0 ? s_key[q0 - 1] : 0ull;
+        prev = q0 ? s_key[kslot(q0 - 1)] : 0ull;
 #pragma unroll
         for (uint32_t e = 0; e < kMaxPer; ++e) {
             rank[e] = pos[e] = 0;
             if (e < per) {
                 const uint32_t q = q0 + e;
-                const unsigned long long k = s_key[q];
+                const unsigned long long k = s_key[kslot(q)];
                 if (q < m && (q == 0 || (k >> kPosBits) != (prev >> kPosBits))) run = q;
                 rank[e] = run;
                 pos[e] = (uint32_t)(k & kPosMask);
@@ -165,7 +237,7 @@ __global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__
         lds_sync();  // every sorted key has been read
 #pragma unroll
         for (uint32_t e = 0; e < kMaxPer; ++e)
-            if (e < per && q0 + e < m) s_key[pos[e]] = rank[e];
+            if (e < per && q0 + e < m) s_key[kslot(pos[e])] = rank[e];
         lds_sync();
         unsigned long long nk[kMaxPer];
 #pragma unroll
@@ -174,20 +246,20 @@ __global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__
             nk[e] = ~0ull;
             if (e < per && i < m) {
                 const uint32_t j = i + h < m ? i + h : i + h - m;  // h < m here
-                nk[e] = (s_key[i] << (2 * kPosBits)) | (s_key[j] << kPosBits) | i;
+                nk[e] = (s_key[kslot(i)] << (2 * kPosBits)) | (s_key[kslot(j)] << kPosBits) | i;
             }
         }
         lds_sync();
 #pragma unroll
         for (uint32_t e = 0; e < kMaxPer; ++e)
-            if (e < per) s_key[q0 + e] = nk[e];
+            if (e < per) s_key[kslot(q0 + e)] = nk[e];
         lds_sync();
-        lds_bitonic_sort(s_key, np);
+        lds_bitonic_sort_reg(s_key, np);
     }
 
     // the last column, and the rows of the rotations starting at multiples of `every`
     for (uint32_t q = tid; q < m; q += kBwtThreads) {
-        const uint32_t p = (uint32_t)(s_key[q] & kPosMask);
+        const uint32_t p = (uint32_t)(s_key[kslot(q)] & kPosMask);
         last[lo + q] = s_blk[p ? p - 1 : m - 1];
         if ((p & ((1u << every_log2) - 1)) == 0) rows[(lo + p) >> every_log2] = (uint16_t)q;
     }
