@@ -56,9 +56,15 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: str, kernel: str, source_hash: str):
+def progress(msg: str):
+    """One line on stderr when a part of a long run ends."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def read_traffic(workload: str, kernel: str, source_hash: str, chunk: int, sub: int):
     """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None if there is none or it was taken on different kernel source."""
+    None if there is none or it was taken on different kernel source or with
+    other chunk or sub-block sizes."""
     path = os.path.join(ROOT, "profiles", f"counters_{workload}.txt")
     if not os.path.exists(path):
         return None
@@ -69,6 +75,8 @@ def read_traffic(workload: str, kernel: str, source_hash: str):
                 k, v = line.split(":", 1)
                 kv[k.strip()] = v.strip()
     if kv.get("kernel_source_sha256") != source_hash:
+        return None
+    if kv.get("chunk_size") != str(chunk) or kv.get("sub_size") != str(sub):
         return None
     try:
         return float(kv[f"{kernel}_hbm_bytes_per_launch"])
@@ -239,7 +247,7 @@ def stream_report(P, n: int, chunk: int, sub: int, r: dict, workload: str) -> di
     avg_ms = r["ktime"][dom][0] / max(1, r["ktime"][dom][1])
     achieved = kalg[dom] / (avg_ms * 1e-3) / 1e9
     src_hash = kernel_source_hash()
-    traffic = read_traffic(workload, names[dom], src_hash)
+    traffic = read_traffic(workload, names[dom], src_hash, chunk, sub)
     step_ms = r["compress_ms"] + r["decode_ms"]
     alg = {"compress": 2 * n + T / 8 + index_bytes + P.DCB_BYTES, "decode": T / 8 + n + index_bytes}
     return {
@@ -618,6 +626,7 @@ def serve_leg(P, params: dict, seconds: float, pool_n: int, loads, chunk: int, s
         lat, thr, rate, bad = run(reqs, arr)
         knee.append({"offered_per_s": round(lam, 1), "delivered_per_s": round(rate, 1), "throughput_GBps": round(thr, 2),
                      "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "mismatches": bad})
+        progress(f"serve knee: offered {lam:.1f}/s delivered {rate:.1f}/s, {thr:.1f} GB/s, {bad} mismatches")
     lam_sat = max(k["delivered_per_s"] for k in knee)
     out = {"workload": f"pool of {pool_n} Markov-text requests, sizes log-uniform 1 KiB-64 MiB (mean {mean / 1e6:.2f} MB), "
                        f"70% compress / 30% decompress, 64 GB budget, {seconds:g} s per rate; every request's result "
@@ -636,6 +645,8 @@ def serve_leg(P, params: dict, seconds: float, pool_n: int, loads, chunk: int, s
                              "throughput_GBps": round(thr, 2), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 3),
                              "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 3), "mismatches": bad,
                              "all_ok": bad == 0})
+        progress(f"serve load {f}: {count} requests, {thr:.1f} GB/s, p50 {np.percentile(lat, 50) * 1e3:.2f} ms, "
+                 f"p99 {np.percentile(lat, 99) * 1e3:.2f} ms, {bad} mismatches")
     st = srv.stats()
     out["batches"] = st["batches"]
     out["all_ok"] = bool(all_ok)
@@ -770,15 +781,18 @@ def main():
         if not args.no_segments:
             ps["segments"] = segments_leg(P, codec, x2, rep2["T"], args.segment, s2, 20)
         line["paper_scale"] = ps
+        progress("markov_45MiB leg done")
         del r2, x2
         torch.cuda.empty_cache()
     codec.close()
     if not args.no_method3:
         line["method3"] = [method3_leg(P, params, wl, 16384, 256, 256 << 10, 128, 5, flush, not args.no_cpu)
                            for wl in ("words_45MiB", "markov_45MiB")]
+        progress("method 3 leg done")
         torch.cuda.empty_cache()
     if not args.no_batch:
         line["batch"] = batch_leg(P, params, args.batch_files, 10, 256 << 10, sub)
+        progress("batch leg done")
         torch.cuda.empty_cache()
     if not args.no_serve:
         line["serving"] = serve_leg(P, params, args.serve_seconds, args.serve_pool,

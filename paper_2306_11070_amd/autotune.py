@@ -8,8 +8,9 @@ the choices in a JSON cache.  Every candidate produces the same bits (the
 parameters change only how the work is split), so the tuner needs no
 correctness check beyond the library's own status word.
 
-Each phase is tuned on its own: the histogram does not depend on the encode
-or decode settings, the encode only on its workgroups per CU, the decode on
+Each phase is tuned on its own: the histogram (timed inside compress, where
+it also writes the per-tile histograms) does not depend on the encode or
+decode settings, the encode only on its workgroups per CU, the decode on
 the sub-block size and the direct-decode workgroup size.  The chunk size is
 chosen last, from the decode-index budget: the smallest chunk whose index
 (8 bytes per chunk + 4 per sub-block) stays under `max_index_frac` of the
@@ -105,6 +106,25 @@ def _time_ms(fn, reps: int) -> float:
     return ts[len(ts) // 2]
 
 
+def _kernel_ms(codec, kernel: str, fn, reps: int) -> float:
+    """Median time of one kernel's launches inside `fn`, from the context's
+    HIP events around them."""
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    codec.set_timing(True)
+    codec.kernel_time(kernel)  # clears
+    ts = []
+    for _ in range(reps):
+        fn()
+        torch.cuda.synchronize()
+        ms, k = codec.kernel_time(kernel)
+        ts.append(ms / max(1, k))
+    codec.set_timing(False)
+    ts.sort()
+    return ts[len(ts) // 2]
+
+
 def tune(x, space: dict | None = None, reps: int = 5, max_index_frac: float = 0.08, cache: Cache | None = None,
          use_cache: bool = True, device: int = 0) -> dict:
     """Tunes on the device tensor `x` (uint8).  Returns the chosen settings
@@ -131,13 +151,19 @@ def tune(x, space: dict | None = None, reps: int = 5, max_index_frac: float = 0.
     t_start = time.time()
     result = {"key": key, "n": n, "bits_per_byte": bpb}
 
-    # histogram: depth x workgroups
+    # histogram: depth x workgroups, timed inside compress (where it also
+    # writes the per-tile histograms the encoder's offsets come from), from
+    # the context's own events around the histogram launch
     ht = {}
+    cout = dict(hist=torch.empty(256, dtype=torch.int64, device=x.device),
+                dcb=torch.empty(P.DCB_BYTES, dtype=torch.uint8, device=x.device),
+                words=torch.empty((n + 3) // 4 + 8, dtype=torch.int32, device=x.device),
+                chunk_off=torch.empty((n >> 20) + 2, dtype=torch.int64, device=x.device))
     for d, b in itertools.product(sp["hist_depth"], sp["hist_blocks_per_cu"]):
         c = P.Codec(device, dict(hist_depth=d, hist_blocks=b * ncu))
-        out = torch.empty(256, dtype=torch.int64, device=x.device)
-        ht[(d, b)] = _time_ms(lambda: c.histogram(x, out=out), reps)
+        ht[(d, b)] = _kernel_ms(c, "hist", lambda: c.compress(x, 1 << 20, out=cout), reps)
         c.close()
+    del cout
     (hd, hb) = pick_min(ht)
     result.update(hist_depth=hd, hist_blocks=hb * ncu, hist_ms=ht[(hd, hb)])
 
