@@ -1,17 +1,25 @@
 // HIP kernels of the Huffman codec for gfx950 (CDNA4, wave64).
 //
-//   k_hist      byte histogram: LDS-privatised replicated counters, one
-//               global atomic per bin per workgroup, self-resetting
-//               accumulator finalised by the last workgroup.
-//   k_codebook  tie-ruled Huffman code lengths, canonical codes and decode
-//               tables for one file per workgroup.
-//   k_encode    single-pass chunked encode: code lengths per 16-byte unit,
-//               workgroup scan, decoupled look-back across tiles for the
-//               tile's first stream bit, LDS-staged bit packing, coalesced
-//               word stores, segment index and decode index.
-//   k_decode    one lane per indexed sub-block (or chunk): table-driven
-//               canonical decode from a 64-bit bit window.
-//   k_copy      plain 16-byte copy, the bandwidth probe.
+//   k_hist            byte histogram over 16 KiB tiles: replicated LDS
+//                     counters, a u16 histogram per tile (what the tile
+//                     offsets come from), totals added into accumulator
+//                     copies that the consumer sums and clears.
+//   k_hist_finalize   sums the accumulator copies (histogram-only calls).
+//   k_codebook        tie-ruled Huffman code lengths, canonical codes and
+//                     decode tables, one workgroup per file.
+//   k_tile_bits_hist  code bits of each tile from its histogram.
+//   k_tile_scan       exclusive scan of the tile bits (block carries summed in
+//                     the same launch up to eight scan blocks);
+//   k_tile_scan_seg,  otherwise, or per file in a batch: segmented block scans
+//   k_blk_scan        and a scan of the block totals with resets.
+//   k_encode          one workgroup per tile: per-thread code packing, a
+//                     workgroup scan of the bit counts, words assembled in LDS
+//                     and stored coalesced, segment and decode index entries.
+//   k_decode_lds      one lane per sub-block, the wave's stream staged in LDS,
+//                     table-driven decode, bytes stored through LDS.
+//   k_decode          one lane per sub-block or chunk read from memory.
+//   k_copy            plain copy, the bandwidth probe and counter calibration.
+//   k_compare         device comparison of results with expected bytes.
 #include "common.h"
 
 #include <mutex>
@@ -29,11 +37,6 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x) {
     return x;
 }
 
-// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
-// every outstanding global load and store of the wave (it is a workgroup
-// release/acquire on all memory), which would drain the next tile's prefetch
-// and the current tile's stores at each barrier.  Used where the threads of
-// a workgroup share data through LDS alone.
 // Inclusive prefix sum of a u64 across the 64 lanes of a wave.
 __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
     const uint32_t lane = threadIdx.x & 63;
@@ -45,6 +48,11 @@ __device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t x) {
     return x;
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load and store of the wave (it is a workgroup
+// release/acquire on all memory), which would drain the next tile's prefetch
+// and the current tile's stores at each barrier.  Used where the threads of
+// a workgroup share data through LDS alone.
 __device__ __forceinline__ void lds_barrier() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
     __builtin_amdgcn_s_barrier();
@@ -820,6 +828,14 @@ constexpr int kSlotStride = kEncThreads + 1;           // word k of thread t at 
 constexpr int kLinRow = kEncUnit * 8 / 32 + 1;
 static_assert((kSlotWords - kLinRow) * kSlotStride >= kEncTile * 8 / 32 + 1, "tile words fit above the slots");
 constexpr int kEncWaves = kEncThreads / 64;
+// The compact encode kernel: codes of at most 10 bits, so a slot needs 21
+// words and the zero word, and a tile at most 16 KiB x 10 / 32 + 1 words,
+// which the whole slot region holds once the threads have taken their words
+// into registers.  Its LDS (about 26.8 KB against 38.4 KB) lets a CU hold six
+// workgroups instead of four, so more tiles' loads are in flight.
+constexpr int kEncCompactMaxLen = 10;
+constexpr int kCompactRows = kEncUnit * kEncCompactMaxLen / 32 + 2;
+static_assert(kCompactRows * kSlotStride >= kEncTile * kEncCompactMaxLen / 32 + 1, "a tile's words fit the slots");
 
 __device__ __forceinline__ uint32_t byte64(const uint4& a, const uint4& b, const uint4& c, const uint4& d, int i) {
     return i < 16 ? byte_of(a, i) : i < 32 ? byte_of(b, i - 16) : i < 48 ? byte_of(c, i - 32) : byte_of(d, i - 48);
@@ -881,9 +897,13 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
     slot[nwp * kSlotStride] = 0;
 }
 
-template <bool kBatch, bool kAligned>
-__global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
-    __shared__ uint32_t s_slot[kSlotWords * kSlotStride];  // private slots; tile bytes (generic path)
+// kRows = kSlotWords: every code length (the full kernel); kRows =
+// kCompactRows: codes of at most kEncCompactMaxLen bits.
+template <bool kBatch, bool kAligned, int kRows>
+__device__ __forceinline__ void encode_tiles(const EncArgs& a) {
+    constexpr bool kCompact = kRows < kSlotWords;
+    static_assert(!kCompact || !kBatch, "the compact kernel codes single streams");
+    __shared__ uint32_t s_slot[kRows * kSlotStride];  // private slots; tile bytes (generic path)
     __shared__ unsigned long long s_code[256];
     __shared__ uint16_t s_code16[256];
     __shared__ uint8_t s_code8[256];
@@ -894,6 +914,11 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
     const uint8_t* s_prev = reinterpret_cast<const uint8_t*>(s_prev4);
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if constexpr (!kBatch) {
+        // a split launch: the stream's codes are the compact kernel's or the
+        // full kernel's, never both (the same value for the whole grid)
+        if (a.split && kCompact != (a.one.cb->max_len <= (uint32_t)kEncCompactMaxLen)) return;
+    }
     const huff_dcb* loaded = nullptr;
     bool fast = true;
     uint32_t group = 1;
@@ -951,7 +976,9 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
     cur.x0 = cur.x1 = cur.x2 = cur.x3 = make_uint4(0, 0, 0, 0);
     cur.before = cur.local = 0;
     cur.carry = 0;
-    if ((uint64_t)blockIdx.x < a.ntiles) fetch(blockIdx.x, cur);
+    // the compact kernel (one tile per workgroup at its usual grid) loads
+    // each tile when it starts it: no registers held for the next one
+    if (!kCompact && (uint64_t)blockIdx.x < a.ntiles) fetch(blockIdx.x, cur);
     // the previous tile stored its words from the slot rows at and above
     // kLinRow: every read of LDS it still makes comes after its barriers, and
     // from those rows only, which the next tile (same codebook, codes of at
@@ -964,12 +991,13 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
         const uint64_t tstart = j * (uint64_t)kEncTile;
         const uint64_t q0 = tstart + (uint64_t)tid * kEncUnit;
         const uint32_t nv = q0 >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q0);
+        if constexpr (kCompact) fetch(g, cur);
         const uint4 x0 = cur.x0, x1 = cur.x1, x2 = cur.x2, x3 = cur.x3;
         const uint32_t prev4 = cur.before;
         const uint64_t S = cur.carry + cur.local;  // the tile's first stream bit
         // the next tile's loads (none after the workgroup's last tile)
         const uint64_t gn = g + gridDim.x;
-        if (gn < a.ntiles) fetch(gn, cur);
+        if (!kCompact && gn < a.ntiles) fetch(gn, cur);
         if (!(prevLin && f.cb == loaded)) __syncthreads();  // the previous tile is done with the LDS slots and tables
         prevLin = false;
         if (tid < 8) s_prev4[tid] = prev4;
@@ -1092,7 +1120,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
             uint32_t* wp = f.words + w0;
             const uint32_t* slot = s_slot + tid;
             uint32_t prevw = prefix;
-            if (capOK && group == 4) {
+            if (capOK && group == 4 && !kCompact) {
                 // Codes of at most 8 bits fill only slot rows below kLinRow:
                 // the tile's words are put together in order in the rows
                 // above, then the whole workgroup stores them, 1 KB of
@@ -1122,11 +1150,12 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
                 const uint32_t t0 = head + 4 * body;
                 if ((uint32_t)tid < nwt - t0) f.words[ws + t0 + tid] = lin[t0 + tid];
                 prevLin = true;
-            } else if (capOK && group == 3) {
-                // Codes of 9 or 10 bits: the slots fill the rows that the
-                // assembled tile would need, so each thread first takes its
-                // (at most kWords3) words into registers; after a barrier the
-                // whole slot region holds the tile's words in order, and the
+            } else if (capOK && (group == 3 || (kCompact && group == 4))) {
+                // Codes of 9 or 10 bits (and, in the compact kernel, all
+                // codes): the slots fill the rows that the assembled tile
+                // would need, so each thread first takes its (at most
+                // kWords3) words into registers; after a barrier the whole
+                // slot region holds the tile's words in order, and the
                 // workgroup stores them as above.
                 constexpr uint32_t kWords3 = kEncUnit * 10 / 32 + 1;
                 const uint64_t ws = S >> 5;
@@ -1139,7 +1168,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
                     prevw = cur;
                 }
                 __syncthreads();  // every thread is done with its slot
-                constexpr uint32_t kAllWords = kSlotWords * kSlotStride;
+                constexpr uint32_t kAllWords = kRows * kSlotStride;
 #pragma unroll
                 for (uint32_t k = 0; k < kWords3; ++k)
                     if (k < nw && at + k < kAllWords) s_slot[at + k] = wv[k];
@@ -1155,7 +1184,7 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
                 }
                 const uint32_t t0 = head + 4 * body;
                 if ((uint32_t)tid < nwt - t0) f.words[ws + t0 + tid] = s_slot[t0 + tid];
-            } else if (capOK) {
+            } else if (capOK && !kCompact) {
                 // single words up to a 16-byte boundary, then 16-byte stores
                 uint32_t k = 0;
                 const uint32_t head = min(nw, ((uint32_t)(0u - (uint32_t)(uintptr_t)wp) & 15u) >> 2);
@@ -1213,13 +1242,39 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
     }
 }
 
+template <bool kBatch, bool kAligned>
+__global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
+    encode_tiles<kBatch, kAligned, kSlotWords>(a);
+}
+
+// At most 80 VGPRs, so that six workgroups (24 waves) fit a CU, as its LDS allows.
+template <bool kAligned>
+__global__ __launch_bounds__(kEncThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_encode_compact(EncArgs a) {
+    encode_tiles<false, kAligned, kCompactRows>(a);
+}
+template __global__ void k_encode_compact<true>(EncArgs);
+
+// A single stream's codebook is on the device when the encode is queued, so
+// for a 16-byte aligned input both kernels are launched: the compact one on
+// the full grid, then the full one on at most kEncLongGrid workgroups (a
+// persistent grid over the tiles); the one whose codes these are not exits at
+// once.  A batch mixes code lengths across files and uses the full kernel
+// alone.
+constexpr uint32_t kEncLongGrid = 1024;
+
 hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s) {
     if (a.files) {
         if (a.aligned) hipLaunchKernelGGL((k_encode<true, true>), dim3(grid), dim3(kEncThreads), 0, s, a);
         else hipLaunchKernelGGL((k_encode<true, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
+    } else if (a.aligned) {
+        EncArgs b = a;
+        b.split = 1;
+        const uint32_t grid2 = grid < kEncLongGrid ? grid : kEncLongGrid;
+        hipLaunchKernelGGL((k_encode_compact<true>), dim3(grid), dim3(kEncThreads), 0, s, b);
+        hipLaunchKernelGGL((k_encode<false, true>), dim3(grid2), dim3(kEncThreads), 0, s, b);
     } else {
-        if (a.aligned) hipLaunchKernelGGL((k_encode<false, true>), dim3(grid), dim3(kEncThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_encode<false, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
+        // an unaligned input's byte-wise loads would make the compact kernel spill
+        hipLaunchKernelGGL((k_encode<false, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
     }
     return hipGetLastError();
 }
