@@ -140,6 +140,11 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
     const bool dbl = a.tile_hist != nullptr && 2 * depth <= (uint32_t)kHistMaxDepth;
     for (uint32_t i = tid; i < (dbl ? 512u : 256u) * depth; i += kHistThreads) sh[i] = 0;
     const uint32_t rep = tid & (depth - 1);
+    // reading a value's replicas: thread tid's row starts at bank
+    // (tid * depth) mod 32, shared by the 32/depth-apart threads of a half
+    // wave; starting each of them at a different replica makes the 32 reads
+    // of a half wave fall on 32 different banks
+    const uint32_t rot = dl <= 5 ? tid >> (5 - dl) : tid;
     uint32_t* set = sh;
     const uint64_t ntiles = kBatch ? a.ntiles : (a.n + kEncTile - 1) / kEncTile;
     const uint64_t t0 = (uint64_t)blockIdx.x * a.tiles_per_block;
@@ -206,7 +211,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
             lds_barrier();
             if (tid < 256) {
                 uint32_t s = 0;  // modulo 2^32: the growth over one tile is exact
-                for (uint32_t r = 0; r < depth; ++r) s += set[(tid << dl) | ((r + tid) & (depth - 1))];
+                for (uint32_t r = 0; r < depth; ++r) s += set[(tid << dl) | ((r + rot) & (depth - 1))];
                 const uint32_t c = s - (odd ? run2 : run);
                 a.tile_hist[t * 256 + tid] = (uint16_t)c;
                 if (odd) run2 = s; else run = s;
@@ -223,7 +228,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
         if (!a.tile_hist) {
             __syncthreads();
             if (tid < 256)
-                for (uint32_t r = 0; r < depth; ++r) total += sh[(tid << dl) | ((r + tid) & (depth - 1))];
+                for (uint32_t r = 0; r < depth; ++r) total += sh[(tid << dl) | ((r + rot) & (depth - 1))];
         }
         if (tid < 256 && total) atomicAdd(&a.st->acc[blockIdx.x % kHistCopies][tid], total);
     }
@@ -628,32 +633,48 @@ __global__ __launch_bounds__(kEncThreads) void k_tile_bits(const uint8_t* in, ui
 }
 
 // Code bits of every tile from its u16 histogram: sum over byte values of
-// count x code length.  One wave per tile; lane l takes values 4l..4l+3, so
-// the tile's 512-byte histogram is one coalesced 8-byte load per lane.  A
-// batch takes each tile's lengths from its file's codebook.
+// count x code length.  One wave per kTbTiles consecutive tiles; lane l takes
+// values 4l..4l+3, so a tile's 512-byte histogram is one coalesced 8-byte
+// load per lane, and the wave issues the loads of all its tiles before it
+// uses any.  A batch takes each tile's lengths from its file's codebook.
+constexpr uint32_t kTbTiles = 4;
+
 template <bool kBatch>
 __global__ __launch_bounds__(256) void k_tile_bits_hist(TileBitsArgs a) {
     const uint32_t lane = threadIdx.x & 63;
-    const uint64_t t = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (t >= a.ntiles) return;  // the whole wave
-    const huff_dcb* cb = a.cb;
-    if constexpr (kBatch) cb = a.files[a.tile_file[t]].cb;
-    const uint2 h = reinterpret_cast<const uint2*>(a.tile_hist + t * 256)[lane];
-    const uint32_t l4 = reinterpret_cast<const uint32_t*>(cb->len)[lane];
-    uint32_t bits = (h.x & 0xffffu) * (l4 & 0xffu) + (h.x >> 16) * ((l4 >> 8) & 0xffu) +
-                    (h.y & 0xffffu) * ((l4 >> 16) & 0xffu) + (h.y >> 16) * (l4 >> 24);
-    // a byte that occurs but has no code (the encoder itself does not check)
-    const bool missing = ((h.x & 0xffffu) && !(l4 & 0xffu)) || ((h.x >> 16) && !(l4 & 0xff00u)) ||
-                         ((h.y & 0xffffu) && !(l4 & 0xff0000u)) || ((h.y >> 16) && !(l4 & 0xff000000u));
-    if (missing) report(kBatch ? a.files[a.tile_file[t]].status : a.status, a.err, HUFF_E_INVAL);
+    const uint64_t t0 = ((uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6)) * kTbTiles;
+    if (t0 >= a.ntiles) return;  // the whole wave
+    uint2 h[kTbTiles];
+    uint32_t l4[kTbTiles];
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) bits += __shfl_xor(bits, d, 64);
-    if (lane == 0) a.tile_bits[t] = bits;
+    for (uint32_t k = 0; k < kTbTiles; ++k) {
+        const uint64_t t = t0 + k < a.ntiles ? t0 + k : t0;
+        const huff_dcb* cb = a.cb;
+        if constexpr (kBatch) cb = a.files[a.tile_file[t]].cb;
+        h[k] = reinterpret_cast<const uint2*>(a.tile_hist + t * 256)[lane];
+        l4[k] = reinterpret_cast<const uint32_t*>(cb->len)[lane];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < kTbTiles; ++k) {
+        const uint64_t t = t0 + k;
+        if (t >= a.ntiles) break;  // the whole wave
+        const uint2 hk = h[k];
+        const uint32_t lk = l4[k];
+        uint32_t bits = (hk.x & 0xffffu) * (lk & 0xffu) + (hk.x >> 16) * ((lk >> 8) & 0xffu) +
+                        (hk.y & 0xffffu) * ((lk >> 16) & 0xffu) + (hk.y >> 16) * (lk >> 24);
+        // a byte that occurs but has no code (the encoder itself does not check)
+        const bool missing = ((hk.x & 0xffffu) && !(lk & 0xffu)) || ((hk.x >> 16) && !(lk & 0xff00u)) ||
+                             ((hk.y & 0xffffu) && !(lk & 0xff0000u)) || ((hk.y >> 16) && !(lk & 0xff000000u));
+        if (missing) report(kBatch ? a.files[a.tile_file[t]].status : a.status, a.err, HUFF_E_INVAL);
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) bits += __shfl_xor(bits, d, 64);
+        if (lane == 0) a.tile_bits[t] = bits;
+    }
 }
 
 hipError_t launch_tile_bits_hist(const TileBitsArgs& a, hipStream_t s) {
     if (a.ntiles == 0) return hipSuccess;
-    const uint64_t blocks = (a.ntiles + 3) / 4;
+    const uint64_t blocks = (a.ntiles + 4 * kTbTiles - 1) / (4 * kTbTiles);
     if (a.files) hipLaunchKernelGGL(k_tile_bits_hist<true>, dim3((uint32_t)blocks), dim3(256), 0, s, a);
     else hipLaunchKernelGGL(k_tile_bits_hist<false>, dim3((uint32_t)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
