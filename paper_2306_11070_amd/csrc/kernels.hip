@@ -162,7 +162,10 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
             return {a.in, a.n, t * (uint64_t)kEncTile};
         }
     };
-    auto count = [&](uint32_t b) { atomicAdd(&set[(b << dl) | rep], 1u); };
+    // counter of value b in this thread's replica: one shift-add per byte
+    // from the replica's column base
+    uint32_t* col = set + rep;
+    auto count = [&](uint32_t b) { atomicAdd(col + (b << dl), 1u); };
     auto count4 = [&](uint32_t w) {
         count(w & 0xffu);
         count((w >> 8) & 0xffu);
@@ -203,6 +206,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
         }
         const bool odd = dbl && ((t - t0) & 1);
         set = odd ? sh + 256 * depth : sh;
+        col = set + rep;
         count16(c0, sr.base + off, sr.n);
         count16(c1, sr.base + kEncTile / 2 + off, sr.n);
         if (a.tile_hist) {
@@ -1677,8 +1681,9 @@ struct LenCmp {
 // bits into a word holds at least 33 bits ahead, enough for K codes of at
 // most maxLen bits and the peek of the last when
 // (K - 1) * maxLen + lutBits <= 33.  NC = 0: lengths from the length table
-// (a length of 0, no code, is kept in emin); NC = 1 or 2: lengths from NC
-// comparisons (LenCmp).  Each byte is packed as soon as it is decoded, so the
+// (a length of 0, no code, is kept in emin); NC = 3: the same for a complete
+// code, where every table entry has a code and nothing is kept; NC = 1 or 2:
+// lengths from NC comparisons (LenCmp).  Each byte is packed as soon as it is decoded, so the
 // table entries do not stay live.  pos: bit position in the buffer, advanced
 // past the S codes.
 template <int S, int K, int NC>
@@ -1704,6 +1709,8 @@ __device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, 
             if constexpr (NC == 0) {
                 len = t.len8[idx];
                 emin = min(emin, len);
+            } else if constexpr (NC == 3) {
+                len = t.len8[idx];
             } else {
                 len = lc.base + (top >= lc.lim1 ? 1u : 0u);
                 if constexpr (NC == 2) len += top >= lc.lim2 ? 1u : 0u;
@@ -1883,7 +1890,13 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
                     for (uint32_t l = maxLen; l >= 1; --l)
                         if (t.cnt[l]) minLen = l;
                     const uint32_t span = maxLen - minLen;
-                    const bool cmp = span <= 2 && k >= 4 && t.first[maxLen] + t.cnt[maxLen] == (1ull << maxLen);
+                    const bool complete = t.first[maxLen] + t.cnt[maxLen] == (1ull << maxLen);
+                    // Comparisons take the table read off the chain from one
+                    // code to the next but cost more VALU per symbol: they pay
+                    // where the LDS buffer of larger sub-blocks keeps few waves
+                    // on a SIMD; with 64-byte sub-blocks (8 waves per SIMD) the
+                    // decoder is bound by VALU issue and reads the table.
+                    const bool cmp = S >= 128 && span <= 2 && k >= 4 && complete;
                     LenCmp lc = {0u, 0u, 0u};
                     if (span == 0) {
                         lc.base = minLen - 1;  // one length: the comparison with 0 always adds 1
@@ -1899,6 +1912,10 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
                     } else if (cmp) {
                         if (k >= 8) dec_lane_fits<S, 8, 1>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                         else dec_lane_fits<S, 4, 1>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    } else if (complete) {
+                        if (k >= 8) dec_lane_fits<S, 8, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        else if (k >= 4) dec_lane_fits<S, 4, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        else dec_lane_fits<S, 3, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     } else if (k >= 8) {
                         dec_lane_fits<S, 8, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     } else if (k >= 4) {
