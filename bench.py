@@ -140,10 +140,13 @@ class Flusher:
             self.buf.fill_(self.k)
 
 
-def run_stream(P, codec, x, chunk: int, sub: int, steps: int, warmup: int, flush: Flusher, graph: bool = False):
+def run_stream(P, codec, x, chunk: int, sub: int, steps: int, warmup: int, flush: Flusher, graph: bool = False,
+               settle_s: float = 0.0):
     """Times `steps` flushed steps (compress + decode, each replayed from a HIP
     graph when `graph`) with HIP events, then the same steps again, eagerly,
-    with the library's per-kernel event timing."""
+    with the library's per-kernel event timing.  Before the `warmup` steps,
+    untimed steps run for `settle_s` seconds: launch times fall over the
+    first tens of milliseconds of sustained work as the GPU's clocks settle."""
     import numpy as np
     import torch
 
@@ -175,6 +178,12 @@ def run_stream(P, codec, x, chunk: int, sub: int, steps: int, warmup: int, flush
         if ev is not None:
             ev[2].record()
 
+    settle_steps = 0
+    t_settle = time.perf_counter() + settle_s
+    while time.perf_counter() < t_settle:
+        step()
+        torch.cuda.synchronize()
+        settle_steps += 1
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
@@ -214,6 +223,7 @@ def run_stream(P, codec, x, chunk: int, sub: int, steps: int, warmup: int, flush
     assert int(status.item()) == 0, f"device status {int(status.item())}"
     assert torch.equal(out, x), "decoded output differs from the input"
     return {"compress_ms": float(np.mean(comp)), "decode_ms": float(np.mean(dec)), "wall_s": wall,
+            "settle_steps": settle_steps,
             "ktime": ktime, "bufs": bufs, "out": out}
 
 
@@ -665,6 +675,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=None, help="chunk bytes (default: the autotuner's choice)")
     ap.add_argument("--sub", type=int, default=None, help="decode sub-block bytes (0: chunk index only)")
     ap.add_argument("--flush-mib", type=int, default=512, help="MiB written between steps (0: none)")
+    ap.add_argument("--settle-s", type=float, default=0.3,
+                    help="seconds of untimed steps before the warm-up steps, while the GPU's clocks settle (0: none)")
     ap.add_argument("--no-tune", action="store_true", help="fixed default launch parameters, no autotuning")
     ap.add_argument("--graph", action="store_true",
                     help="time each call's launches replayed from a HIP graph (measured slower than eager calls)")
@@ -720,7 +732,7 @@ def main():
     if args.sub is not None:
         sub = args.sub
     codec = P.Codec(0, params)
-    r = run_stream(P, codec, x, chunk, sub, args.steps, args.warmup, flush, graph=args.graph)
+    r = run_stream(P, codec, x, chunk, sub, args.steps, args.warmup, flush, graph=args.graph, settle_s=args.settle_s)
     rep = stream_report(P, n, chunk, sub, r, args.workload)
     cp = copy_probe(codec, x, r["out"], flush)
     value = n / (rep["step_ms"] * 1e-3) / 1e9
@@ -743,6 +755,8 @@ def main():
                    "max_code_len": rep["max_len"], "index_bytes": rep["index_bytes"],
                    "stream_over_input": round((rep["T"] / 8 + rep["index_bytes"]) / n, 4),
                    "cache": f"{args.flush_mib} MiB written between steps (not timed)",
+                   "settle": f"{r['settle_steps']} untimed steps over {args.settle_s:g} s before the warm-up steps "
+                             f"(launch times fall while the GPU's clocks settle)",
                    "launch": "each call's launches replayed from a HIP graph" if args.graph else "eager calls",
                    "step": "huff_compress (histogram + device codebook + encode) + huff_decode"},
         "wall_s_timed_steps_incl_flush": round(r["wall_s"], 4),
@@ -772,7 +786,7 @@ def main():
         d2, c2, s2 = WORKLOADS["markov_45MiB"]
         a2 = datagen.workload("markov_45MiB")
         x2 = torch.from_numpy(a2).to(dev)
-        r2 = run_stream(P, codec, x2, c2, s2, 20, 5, flush, graph=args.graph)
+        r2 = run_stream(P, codec, x2, c2, s2, 20, 5, flush, graph=args.graph, settle_s=args.settle_s)
         rep2 = stream_report(P, a2.size, c2, s2, r2, "markov_45MiB")
         ps = {"workload": f"markov_45MiB: {d2}, chunks of {c2} bytes, decode index every {s2} bytes",
               "value_GBps": round(a2.size / (rep2["step_ms"] * 1e-3) / 1e9, 2), "ms_per_step": round(rep2["step_ms"], 4),
