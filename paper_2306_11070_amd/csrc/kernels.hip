@@ -23,6 +23,7 @@
 #include "common.h"
 
 #include <mutex>
+#include <type_traits>
 
 namespace huff {
 
@@ -1387,15 +1388,23 @@ __device__ __forceinline__ uint64_t peek64(const uint32_t* w, uint64_t nwords, u
 // The peek table is split into a length table and a byte table, so that a
 // lookup needs no address scaling or field extraction and the length, which
 // the next lookup waits for, comes straight from its own load.
-struct DecTables {
-    uint8_t len8[1 << HUFF_LUT_BITS];  // peek -> code length; 0: no code of at most lutBits bits
-    uint8_t sym8[1 << HUFF_LUT_BITS];  // peek -> byte
+template <uint32_t B>
+struct DecTablesT {
+    static constexpr uint32_t kBits = B;
+    uint8_t len8[1 << B];  // peek -> code length; 0: no code of at most lutBits bits
+    uint8_t sym8[1 << B];  // peek -> byte
     unsigned long long first[64];
     uint32_t cnt[64], fidx[64];
     uint8_t sorted[256];
 };
+using DecTables = DecTablesT<HUFF_LUT_BITS>;
+// The longer-code decoders' table: 12-bit peeks, so that codes of 11 and 12
+// bits (most of the longer codes a byte alphabet gets) decode from the table.
+constexpr uint32_t kWideLutBits = 12;
+using DecTablesWide = DecTablesT<kWideLutBits>;
 
-__device__ __forceinline__ void load_tables(DecTables& t, const huff_dcb* cb, uint32_t lutBits) {
+template <class Tab>
+__device__ __forceinline__ void load_tables(Tab& t, const huff_dcb* cb, uint32_t lutBits) {
     const uint32_t nl = 1u << min(lutBits, (uint32_t)HUFF_LUT_BITS);
     for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
         const uint32_t e = cb->lut[i];
@@ -1410,9 +1419,43 @@ __device__ __forceinline__ void load_tables(DecTables& t, const huff_dcb* cb, ui
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) t.sorted[i] = cb->sorted_sym[i];
 }
 
+// The wide table of a codebook whose codes are longer than its own peek
+// table (cb->lut_bits = HUFF_LUT_BITS bits): entry i (wideBits bits) repeats
+// the codebook's entry for its first lut_bits bits when that entry has a
+// code; otherwise the code starting with i is longer than lut_bits, and a
+// canonical search over the lengths up to wideBits finds it (0 if it is
+// longer still).  The canonical tables are loaded as by load_tables.
+__device__ __forceinline__ void load_tables_wide(DecTablesWide& t, const huff_dcb* cb, uint32_t wideBits,
+                                                 uint32_t maxLen) {
+    const uint32_t lb = cb->lut_bits, sh = wideBits - lb;
+    for (uint32_t i = threadIdx.x; i < (1u << wideBits); i += blockDim.x) {
+        const uint32_t e = cb->lut[i >> sh];
+        uint32_t len = e >> 8, sym = e & 0xffu;
+        if (len == 0) {
+            for (uint32_t l = lb + 1; l <= wideBits && l <= maxLen; ++l) {
+                const uint64_t c = i >> (wideBits - l);
+                if (c - cb->first_code[l] < cb->count[l]) {
+                    sym = cb->sorted_sym[cb->first_index[l] + (uint32_t)(c - cb->first_code[l])];
+                    len = l;
+                    break;
+                }
+            }
+        }
+        t.len8[i] = (uint8_t)len;
+        t.sym8[i] = (uint8_t)sym;
+    }
+    for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
+        t.first[i] = cb->first_code[i];
+        t.cnt[i] = cb->count[i];
+        t.fidx[i] = cb->first_index[i];
+    }
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) t.sorted[i] = cb->sorted_sym[i];
+}
+
 // Codes longer than the table: canonical search on the top 32 window bits.
 // Returns sym | len << 8, or 0 if no code matches.
-__device__ __noinline__ uint32_t decode_long(const DecTables& t, uint32_t top, uint32_t lutBits, uint32_t maxLen) {
+template <class Tab>
+__device__ __noinline__ uint32_t decode_long(const Tab& t, uint32_t top, uint32_t lutBits, uint32_t maxLen) {
     for (uint32_t l = lutBits + 1; l <= maxLen; ++l) {
         const uint64_t c = top >> (32 - l);
         if (c - t.first[l] < t.cnt[l]) return t.sorted[t.fidx[l] + (uint32_t)(c - t.first[l])] | (l << 8);
@@ -1472,7 +1515,8 @@ struct WinReader {
         c = k = k_;
         win = 0;
     }
-    __device__ __forceinline__ uint32_t next(const DecTables& t, uint32_t lutBits, uint32_t& emin) {
+    template <class Tab>
+    __device__ __forceinline__ uint32_t next(const Tab& t, uint32_t lutBits, uint32_t& emin) {
         if (c == k) {
             pos += cons;
             const uint32_t w = min(pos >> 5, last - 1);
@@ -1493,8 +1537,8 @@ struct WinReader {
 // kFits: every code is at most lutBits long, so the table alone decodes; a
 // table length of 0 (no code matches) is then kept in emin (the least length
 // seen) and reported by the caller instead of being branched on per symbol.
-template <bool kFits, class Rd, typename U>
-__device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+template <bool kFits, class Rd, typename U, class Tab>
+__device__ __forceinline__ uint32_t dec1(Rd& r, const Tab& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
                                          U& used, uint32_t& emin) {
     r.refill();
     const uint32_t top = (uint32_t)(r.win >> 32);
@@ -1516,8 +1560,8 @@ __device__ __forceinline__ uint32_t dec1(Rd& r, const DecTables& t, uint32_t lut
 
 // The windowed reader decodes from the table alone; bits used are counted by
 // its position, not here.
-template <bool kFits, typename U>
-__device__ __forceinline__ uint32_t dec1(WinReader& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+template <bool kFits, typename U, class Tab>
+__device__ __forceinline__ uint32_t dec1(WinReader& r, const Tab& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
                                          U& used, uint32_t& emin) {
     return r.next(t, lutBits, emin);
 }
@@ -1525,8 +1569,8 @@ __device__ __forceinline__ uint32_t dec1(WinReader& r, const DecTables& t, uint3
 constexpr int kDecLine = 64;  // bytes a decode lane stores together
 
 // 16 symbols, packed into 16 bytes in stream order.
-template <bool kFits, class Rd, typename U>
-__device__ __forceinline__ uint4 dec16(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad, U& used,
+template <bool kFits, class Rd, typename U, class Tab>
+__device__ __forceinline__ uint4 dec16(Rd& r, const Tab& t, uint32_t lutBits, uint32_t maxLen, bool& bad, U& used,
                                        uint32_t& emin) {
     uint32_t o[4] = {0, 0, 0, 0};
 #pragma unroll
@@ -1543,8 +1587,8 @@ __device__ __forceinline__ uint4 dec16(Rd& r, const DecTables& t, uint32_t lutBi
 // A lane therefore holds its last kLine / 16 groups of 16 decoded bytes in a
 // register queue and stores them together once kLine bytes are complete, so
 // that every kLine-byte piece of a line is written whole.
-template <int kLine, bool kFits, class Rd, typename U>
-__device__ __forceinline__ void dec_run_k(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+template <int kLine, bool kFits, class Rd, typename U, class Tab>
+__device__ __forceinline__ void dec_run_k(Rd& r, const Tab& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
                                           U& used, uint8_t* out, uint32_t nsym) {
     uint32_t emin = 0xffffffffu;
     constexpr uint32_t kG = kLine / 16;  // groups held before they are stored
@@ -1574,15 +1618,16 @@ __device__ __forceinline__ void dec_run_k(Rd& r, const DecTables& t, uint32_t lu
 }
 
 // Picks the table-only decoder when every code fits the table.
-template <int kLine, class Rd, typename U>
-__device__ __forceinline__ void dec_run(Rd& r, const DecTables& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
+template <int kLine, class Rd, typename U, class Tab>
+__device__ __forceinline__ void dec_run(Rd& r, const Tab& t, uint32_t lutBits, uint32_t maxLen, bool& bad,
                                         U& used, uint8_t* out, uint32_t nsym) {
     if (maxLen <= lutBits) dec_run_k<kLine, true>(r, t, lutBits, maxLen, bad, used, out, nsym);
     else dec_run_k<kLine, false>(r, t, lutBits, maxLen, bad, used, out, nsym);
 }
 
 // Codes longer than 32 bits: canonical search on a 64-bit peek from memory.
-__device__ void decode_generic(const FileDesc& f, const DecTables& t, uint32_t maxLen, uint64_t start, uint64_t nsym,
+template <class Tab>
+__device__ void decode_generic(const FileDesc& f, const Tab& t, uint32_t maxLen, uint64_t start, uint64_t nsym,
                                uint8_t* out, bool& bad, uint64_t& used) {
     uint64_t pos = start;
     for (uint64_t i = 0; i < nsym; ++i) {
@@ -1686,8 +1731,8 @@ struct LenCmp {
 // lengths from NC comparisons (LenCmp).  Each byte is packed as soon as it is decoded, so the
 // table entries do not stay live.  pos: bit position in the buffer, advanced
 // past the S codes.
-template <int S, int K, int NC>
-__device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, uint32_t& pos, const DecTables& t,
+template <int S, int K, int NC, class Tab>
+__device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, uint32_t& pos, const Tab& t,
                                               uint32_t lutBits, const LenCmp lc, uint4 (&o)[S / 16],
                                               uint32_t& emin) {
     uint64_t win = 0;
@@ -1807,34 +1852,46 @@ enum : int { kDecFits = 0, kDecLong = 1, kDecBoth = 2 };
 // last sub-block of a stream is decoded byte by byte.  Longer codes: each
 // lane decodes with a refilled window and stores 64 bytes at a time; codes
 // longer than 32 bits are decoded straight from memory.
-template <int S>
+template <int S, class Tab>
 struct StagedLds {
     uint32_t in[4][64 * S / 4 + 8];
-    DecTables t;
+    Tab t;
 };
+// The tables a staged launch takes: the longer-code launch (a kernel of its
+// own below 128-byte sub-blocks) peeks 12 bits.
+template <int S, int kMode>
+using StagedLdsFor = StagedLds<S, typename std::conditional<kMode == kDecLong, DecTablesWide, DecTables>::type>;
 
 // One block of 256 decode lanes (`blk`); every return below is either taken
 // by the whole workgroup or comes after the workgroup's last barrier.
 template <int S, bool kBatch, int kMode>
-__device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk, StagedLds<S>& sm) {
+__device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk, StagedLdsFor<S, kMode>& sm) {
     constexpr uint32_t kInWords = 64 * S / 4 + 8;
     constexpr uint32_t G = S / 16;
     constexpr int kLine = S < kDecLine ? S : kDecLine;
     auto& s_in = sm.in;
-    DecTables& t = sm.t;
+    auto& t = sm.t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     FileDesc f;
     if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, blk * 256)];
     else f = a.one;
     const huff_dcb* cb = f.cb;
-    const uint32_t lutBits = cb->lut_bits, maxLen = cb->max_len;
-    const bool fits = maxLen <= lutBits;
-    if (kMode != kDecBoth && fits != (kMode == kDecFits)) return;  // the other launch decodes this block
-    if (maxLen == 0 || maxLen > HUFF_MAX_CODE_LEN || lutBits == 0 || lutBits > HUFF_LUT_BITS) {
+    const uint32_t cbBits = cb->lut_bits, maxLen = cb->max_len;
+    if (kMode != kDecBoth && (maxLen <= cbBits) != (kMode == kDecFits)) return;  // the other launch decodes this block
+    if (maxLen == 0 || maxLen > HUFF_MAX_CODE_LEN || cbBits == 0 || cbBits > HUFF_LUT_BITS) {
         if (tid == 0) report(f.status, a.err, HUFF_E_CORRUPT);
         return;
     }
-    load_tables(t, cb, lutBits);
+    // the longer-code launch peeks up to kWideLutBits bits: codes that fit
+    // them decode from the table alone, like the first launch's
+    uint32_t lutBits = cbBits;
+    if constexpr (kMode == kDecLong) {
+        lutBits = min(maxLen, kWideLutBits);
+        load_tables_wide(t, cb, lutBits, maxLen);
+    } else {
+        load_tables(t, cb, lutBits);
+    }
+    const bool fits = maxLen <= lutBits;
 
     const uint64_t n = f.n;
     const uint64_t nitems = (n + S - 1) / S;
@@ -1915,13 +1972,16 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
                     } else if (complete) {
                         if (k >= 8) dec_lane_fits<S, 8, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                         else if (k >= 4) dec_lane_fits<S, 4, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
-                        else dec_lane_fits<S, 3, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        else if (k >= 3) dec_lane_fits<S, 3, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        else dec_lane_fits<S, 2, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     } else if (k >= 8) {
                         dec_lane_fits<S, 8, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     } else if (k >= 4) {
                         dec_lane_fits<S, 4, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
-                    } else {
+                    } else if (k >= 3) {
                         dec_lane_fits<S, 3, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    } else {
+                        dec_lane_fits<S, 2, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     }
                     used = pos - bit0;
                     if ((j0 + 64) * S <= n) {
@@ -1991,7 +2051,7 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
 // One workgroup per block of 256 lanes.
 template <int S, bool kBatch, int kMode>
 __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
-    __shared__ StagedLds<S> sm;
+    __shared__ StagedLdsFor<S, kMode> sm;
     dec_staged_block<S, kBatch, kMode>(a, blockIdx.x, sm);
 }
 
@@ -2000,7 +2060,7 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
 // table-only path registers, about 64 -> 107 VGPRs at 64 bytes).
 template <int S, bool kBatch>
 __global__ __launch_bounds__(256) void k_decode_lds_long(DecArgs a) {
-    __shared__ StagedLds<S> sm;
+    __shared__ StagedLdsFor<S, kDecLong> sm;
     const uint64_t nblk = (a.nitems + 255) / 256;
     for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         dec_staged_block<S, kBatch, kDecLong>(a, blk, sm);

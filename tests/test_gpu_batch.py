@@ -256,3 +256,30 @@ def test_batch_scan_carries_across_blocks(P, codec):
             _check_file(f, a, chunk, sub, r)
             assert torch.equal(f["out"], xs[i]), (rep, i)
     b.close()
+
+
+def test_batch_codes_past_the_table(P, codec):
+    """Files whose longest codes are 9, 11, 12, 13 and 15 bits in one batch:
+    the longer-code decode launch takes the files past the 10-bit table and
+    decodes codes of up to 12 bits from its 12-bit table.  Every file against
+    the oracle alone, and decoded back."""
+    data = []
+    for i, L in enumerate([9, 11, 12, 13, 15, 11]):
+        M = (1 << 19) >> L
+        counts = [M << (L - 1 - k) for k in range(L)] + [M]
+        a = np.repeat((np.arange(L + 1) * 11 + 1).astype(np.uint8), counts)
+        np.random.default_rng(40 + i).shuffle(a)
+        data.append(a[: a.size - 3 * i])  # ragged ends
+    _say(f"batch past the table: {len(data)} files")
+    for sub in (32, 64):
+        chunk = 16384
+        xs = [dev(a) for a in data]
+        files = P.batch_buffers(codec, xs, chunk, sub)
+        b = P.Batch(codec, files, chunk, sub)
+        b.compress()
+        b.decode()
+        torch.cuda.synchronize()
+        for f, a, x in zip(files, data, xs):
+            _check_file(f, a, chunk, sub)
+            assert torch.equal(f["out"], x)
+        b.close()

@@ -103,6 +103,30 @@ def test_staged_long_codes(codec, sub):
     _roundtrip(codec, a, 4096, sub)
 
 
+def _dyadic(L, seed):
+    """About 1 MiB whose Huffman code has the lengths 1, 2, ..., L, L exactly
+    (counts M * 2^(L-1), ..., M * 2, M, M, each count of a value halving the
+    one before, shuffled): a code of L bits at most, with every length."""
+    M = (1 << 20) >> L
+    counts = [M << (L - 1 - i) for i in range(L)] + [M]
+    a = np.repeat((np.arange(L + 1) * 7 + 3).astype(np.uint8), counts)
+    np.random.default_rng(seed).shuffle(a)
+    return a
+
+
+@pytest.mark.parametrize("L", [11, 12, 13, 16])
+@pytest.mark.parametrize("sub", [32, 64])
+def test_staged_wide_table(codec, sub, L):
+    """Codes just past the 10-bit table: the longer-code launch peeks 12 bits,
+    so 11- and 12-bit codes decode from its table (two or three codes per
+    window), 13 bits and more by canonical search."""
+    _say(f"staged wide table sub={sub} L={L}")
+    a = _dyadic(L, seed=L)
+    r = oracle.compress(a, 4096, sub=sub)
+    assert int(oracle.code_lengths(r["hist"]).max()) == L
+    _roundtrip(codec, a, 4096, sub)
+
+
 @pytest.mark.parametrize("long_codes", [False, True])
 @pytest.mark.parametrize("sub", STAGED)
 def test_staged_in_parts(codec, sub, long_codes):
