@@ -56,8 +56,8 @@ struct EncArgs {
     const uint32_t* tile_local;            // tile's first bit inside its scan block (and, batch, its file)
     const unsigned long long* blk_carry;   // bits of the file open at a block's start, before the block
     int32_t* err;           // fallback status word
-    uint32_t split;         // single stream, set by launch_encode: the compact kernel takes codes of at most
-                            // kEncCompactMaxLen bits, the full kernel the longer ones (each exits on the other's)
+    uint32_t split;         // set by launch_encode: 1 a single stream, 2 a batch, split between the compact kernel
+                            // (codes of at most kEncCompactMaxLen bits) and the full kernel (longer codes)
 };
 
 // Tile offsets are a scan in two levels.  A short stream: k_tile_scan scans

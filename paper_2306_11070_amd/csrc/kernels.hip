@@ -928,7 +928,6 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
 template <bool kBatch, bool kAligned, int kRows>
 __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
     constexpr bool kCompact = kRows < kSlotWords;
-    static_assert(!kCompact || !kBatch, "the compact kernel codes single streams");
     __shared__ uint32_t s_slot[kRows * kSlotStride];  // private slots; tile bytes (generic path)
     __shared__ unsigned long long s_code[256];
     __shared__ uint16_t s_code16[256];
@@ -1004,7 +1003,11 @@ __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
     cur.carry = 0;
     // the compact kernel (one tile per workgroup at its usual grid) loads
     // each tile when it starts it: no registers held for the next one
-    if (!kCompact && (uint64_t)blockIdx.x < a.ntiles) fetch(blockIdx.x, cur);
+    // so does either kernel of a split batch, each of which skips the other's
+    // tiles (a prefetch could read a tile that this kernel then skips)
+    const bool batchSplit = kBatch && a.split == 2;
+    const bool early = kCompact || batchSplit;
+    if (!early && (uint64_t)blockIdx.x < a.ntiles) fetch(blockIdx.x, cur);
     // the previous tile stored its words from the slot rows at and above
     // kLinRow: every read of LDS it still makes comes after its barriers, and
     // from those rows only, which the next tile (same codebook, codes of at
@@ -1012,18 +1015,23 @@ __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
     bool prevLin = false;
     for (uint64_t g = blockIdx.x; g < a.ntiles; g += gridDim.x) {
         const FileDesc& f = fileOf(g);
+        if constexpr (kBatch) {
+            // a split batch: files with codes of at most kEncCompactMaxLen
+            // bits are the compact kernel's, the others the full kernel's
+            if (batchSplit && (f.cb->max_len <= (uint32_t)kEncCompactMaxLen) != kCompact) continue;
+        }
         const uint64_t j = g - f.first;
         const uint64_t n = f.n;
         const uint64_t tstart = j * (uint64_t)kEncTile;
         const uint64_t q0 = tstart + (uint64_t)tid * kEncUnit;
         const uint32_t nv = q0 >= n ? 0u : (uint32_t)min<uint64_t>(kEncUnit, n - q0);
-        if constexpr (kCompact) fetch(g, cur);
+        if (early) fetch(g, cur);
         const uint4 x0 = cur.x0, x1 = cur.x1, x2 = cur.x2, x3 = cur.x3;
         const uint32_t prev4 = cur.before;
         const uint64_t S = cur.carry + cur.local;  // the tile's first stream bit
         // the next tile's loads (none after the workgroup's last tile)
         const uint64_t gn = g + gridDim.x;
-        if (!kCompact && gn < a.ntiles) fetch(gn, cur);
+        if (!early && gn < a.ntiles) fetch(gn, cur);
         if (!(prevLin && f.cb == loaded)) __syncthreads();  // the previous tile is done with the LDS slots and tables
         prevLin = false;
         if (tid < 8) s_prev4[tid] = prev4;
@@ -1274,29 +1282,34 @@ __global__ __launch_bounds__(kEncThreads) void k_encode(EncArgs a) {
 }
 
 // At most 80 VGPRs, so that six workgroups (24 waves) fit a CU, as its LDS allows.
-template <bool kAligned>
+template <bool kBatch>
 __global__ __launch_bounds__(kEncThreads) __attribute__((amdgpu_waves_per_eu(6, 8))) void k_encode_compact(EncArgs a) {
-    encode_tiles<false, kAligned, kCompactRows>(a);
+    encode_tiles<kBatch, true, kCompactRows>(a);
 }
-template __global__ void k_encode_compact<true>(EncArgs);
 
 // A single stream's codebook is on the device when the encode is queued, so
 // for a 16-byte aligned input both kernels are launched: the compact one on
 // the full grid, then the full one on at most kEncLongGrid workgroups (a
 // persistent grid over the tiles); the one whose codes these are not exits at
-// once.  A batch mixes code lengths across files and uses the full kernel
-// alone.
+// once.  A batch of aligned files launches both on the full grid, each taking
+// the tiles of the files whose codes are its own.
 constexpr uint32_t kEncLongGrid = 1024;
 
 hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s) {
     if (a.files) {
-        if (a.aligned) hipLaunchKernelGGL((k_encode<true, true>), dim3(grid), dim3(kEncThreads), 0, s, a);
-        else hipLaunchKernelGGL((k_encode<true, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
+        if (a.aligned) {
+            EncArgs b = a;
+            b.split = 2;
+            hipLaunchKernelGGL((k_encode_compact<true>), dim3(grid), dim3(kEncThreads), 0, s, b);
+            hipLaunchKernelGGL((k_encode<true, true>), dim3(grid), dim3(kEncThreads), 0, s, b);
+        } else {
+            hipLaunchKernelGGL((k_encode<true, false>), dim3(grid), dim3(kEncThreads), 0, s, a);
+        }
     } else if (a.aligned) {
         EncArgs b = a;
         b.split = 1;
         const uint32_t grid2 = grid < kEncLongGrid ? grid : kEncLongGrid;
-        hipLaunchKernelGGL((k_encode_compact<true>), dim3(grid), dim3(kEncThreads), 0, s, b);
+        hipLaunchKernelGGL((k_encode_compact<false>), dim3(grid), dim3(kEncThreads), 0, s, b);
         hipLaunchKernelGGL((k_encode<false, true>), dim3(grid2), dim3(kEncThreads), 0, s, b);
     } else {
         // an unaligned input's byte-wise loads would make the compact kernel spill
