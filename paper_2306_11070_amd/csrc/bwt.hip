@@ -5,8 +5,8 @@
 //            prefix doubling (position-tagged rank keys sorted in LDS), the
 //            last column out, and the row of every rotation that starts at a
 //            multiple of `every` (the inverse starts its walks there).
-//   k_mtf    one wave per block: move-to-front positions, the 256-entry list
-//            held four bytes per lane.
+//   k_mtf    one wave per block: move-to-front positions, the list's first
+//            64 entries one per lane, the rest in LDS.
 //   k_unmtf  one wave per block: the inverse.
 //   k_unbwt  one workgroup per block: the last-to-first map from a stable
 //            count of the last column (wave ballots), then one walker per
@@ -266,51 +266,68 @@ __global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__
 }
 
 // ------------------------------------------------------- move to front
-// One wave per block.  The list of the 256 byte values is spread over the
-// wave, four entries per lane: byte j of lane l is list position 4l + j.  A
-// lane reads 64 input bytes at a time; the wave then takes them in order,
-// each as a uniform value: the lane whose word holds the byte (a zero-byte
-// test of the word xor the byte) gives the position, and every entry before
-// that position moves one place back (each lane shifts its word up a byte
-// and takes the previous lane's top byte), the byte going to the front.
+// One wave per block.  List positions 0..63 are held one per lane (lane l
+// holds the byte at position l); positions 64..255 sit in a per-wave LDS
+// array.  A lane reads 64 input bytes at a time; the wave then takes them in
+// order, each as a uniform value.  Forward: a ballot of the lanes equal to
+// the byte gives its position; the rare byte further back is found by three
+// ballots over the LDS part.  Inverse: the position names the lane (or LDS
+// entry) that holds the byte.  Then every entry before the position moves one
+// place back (a DPP shift of the wave by one lane; with a position past 63,
+// lane 63's entry and the LDS entries before the position move too) and the
+// byte goes to the front.  After a block transform nearly every position is
+// small, so a byte costs a few wave instructions.
 template <bool kInverse>
 __global__ __launch_bounds__(256) void k_mtf(const uint8_t* __restrict__ in, uint64_t n, uint32_t block,
                                              uint8_t* __restrict__ out) {
+    __shared__ uint32_t s_tail[4][192];
     const uint32_t lane = threadIdx.x & 63;
     const uint64_t b = (uint64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const uint64_t lo = b * block;
     if (lo >= n) return;  // the whole wave
     const uint32_t m = (uint32_t)min<uint64_t>(block, n - lo);
-    uint32_t w = (4 * lane) | (4 * lane + 1) << 8 | (4 * lane + 2) << 16 | (4 * lane + 3) << 24;
+    uint32_t* tail = s_tail[threadIdx.x >> 6];
+    uint32_t w = lane;  // the list in value order
+    for (uint32_t k = lane; k < 192; k += 64) tail[k] = 64 + k;
+    wave_lds_barrier();
     for (uint32_t base = 0; base < m; base += 64) {
         const uint32_t cnt = min(64u, m - base);
         const uint32_t v = lane < cnt ? in[lo + base + lane] : 0u;
         uint32_t res = 0;
         for (uint32_t t = 0; t < cnt; ++t) {
             const uint32_t x = __builtin_amdgcn_readlane(v, t);
-            uint32_t at, j, c;
+            uint32_t at, c;
             if constexpr (!kInverse) {
                 c = x;
-                const uint32_t d = w ^ (c * 0x01010101u);
-                const uint32_t z = (d - 0x01010101u) & ~d & 0x80808080u;  // lowest set bit: first zero byte
-                const uint64_t hit = __ballot(z != 0);
-                at = (uint32_t)__builtin_ctzll(hit);
-                j = (uint32_t)__builtin_ctz(__builtin_amdgcn_readlane(z, at)) >> 3;
+                const uint64_t hit = __ballot(w == c);
+                if (hit) {
+                    at = (uint32_t)__builtin_ctzll(hit);
+                } else {
+                    const uint64_t h0 = __ballot(tail[lane] == c), h1 = __ballot(tail[64 + lane] == c);
+                    const uint64_t h2 = __ballot(tail[128 + lane] == c);
+                    at = 64 + (h0 ? (uint32_t)__builtin_ctzll(h0)
+                                  : h1 ? 64 + (uint32_t)__builtin_ctzll(h1) : 128 + (uint32_t)__builtin_ctzll(h2));
+                }
             } else {
-                at = x >> 2;
-                j = x & 3;
-                c = (__builtin_amdgcn_readlane(w, at) >> (8 * j)) & 0xffu;
+                at = x;
+                c = at < 64 ? __builtin_amdgcn_readlane(w, at) : tail[at - 64];
             }
-            // entries before position 4*at + j move back one place; c goes to
-            // the front.  The previous lane's top byte comes by a DPP shift of
-            // the whole wave by one lane (no LDS round trip); lane 0 takes c.
-            uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp((int)c, (int)(w >> 24), 0x138 /* wave_shr:1 */, 0xf,
-                                                                0xf, false);
-            const uint32_t sh = (w << 8) | up;
-            const uint32_t keep = j == 3 ? 0u : 0xffffffffu << (8 * (j + 1));  // bytes after position j stay
-            if (lane < at) w = sh;
-            else if (lane == at) w = (w & keep) | (sh & ~keep);
-            if (lane == t) res = kInverse ? c : 4 * at + j;
+            if (at >= 64) {
+                // LDS entries [0, at - 64] move one place back, lane 63's entry to the first of them
+                const uint32_t p = at - 64, last = __builtin_amdgcn_readlane(w, 63);
+                const uint32_t q0 = lane ? tail[lane - 1] : last, q1 = tail[63 + lane], q2 = tail[127 + lane];
+                wave_lds_barrier();
+                if (lane <= p) tail[lane] = q0;
+                if (64 + lane <= p) tail[64 + lane] = q1;
+                if (128 + lane <= p) tail[128 + lane] = q2;
+                wave_lds_barrier();
+            }
+            // lanes up to the position (all of them past 63) take the previous
+            // lane's entry by a DPP shift of the wave by one lane; lane 0 takes c
+            const uint32_t sh = (uint32_t)__builtin_amdgcn_update_dpp((int)c, (int)w, 0x138 /* wave_shr:1 */, 0xf, 0xf,
+                                                                      false);
+            w = lane <= at ? sh : w;
+            res = lane == t ? (kInverse ? c : at) : res;
         }
         if (lane < cnt) out[lo + base + lane] = (uint8_t)res;
     }
