@@ -21,6 +21,8 @@ namespace {
 constexpr int kBwtThreads = 1024;
 constexpr uint32_t kPosBits = 14;  // positions and ranks in a block of at most 2^14 bytes
 constexpr uint64_t kPosMask = (1u << kPosBits) - 1;
+constexpr uint32_t kKeyBytes = 6;  // the first sort's key: 6 bytes and the position (62 bits)
+static_assert(8 * kKeyBytes + kPosBits < 64, "first keys stay below the padding key");
 constexpr uint32_t kMaxPer = HUFF_BWT_MAX_BLOCK / kBwtThreads;  // sort slots per thread
 static_assert(HUFF_BWT_MAX_BLOCK == 1u << kPosBits, "block positions fit kPosBits");
 
@@ -167,9 +169,9 @@ __device__ __forceinline__ uint32_t wg_sum(uint32_t v, uint32_t* s_red) {
 
 // ------------------------------------------------------------ forward
 // One workgroup per block of m <= 16384 bytes.  A key is
-// (group value << 14) | position: first the rotation's first four bytes, then,
+// (group value << 14) | position: first the rotation's first six bytes, then,
 // once ranks exist, (rank, rank of the rotation h bytes further) -- so the
-// sorted keys order the rotations by their first 4, 8, 16, ... bytes, with
+// sorted keys order the rotations by their first 6, 12, 24, ... bytes, with
 // ties in start position.  Each round gives every rotation the slot of the
 // first key of its group as its rank, stops when all ranks differ (or when
 // h >= m: rotations still tied are equal and stay in start order), and
@@ -195,16 +197,21 @@ __global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__
         const uint32_t i = q0 + e;
         unsigned long long k = ~0ull;
         if (i < m) {
-            const uint32_t c4 = (uint32_t)s_blk[i] << 24 | (uint32_t)s_blk[(i + 1) % m] << 16 |
-                                (uint32_t)s_blk[(i + 2) % m] << 8 | (uint32_t)s_blk[(i + 3) % m];
-            k = ((unsigned long long)c4 << kPosBits) | i;
+            unsigned long long c6 = 0;  // the rotation's first kKeyBytes bytes
+            uint32_t j = i;
+#pragma unroll
+            for (uint32_t t = 0; t < kKeyBytes; ++t) {
+                c6 = (c6 << 8) | s_blk[j];
+                j = j + 1 == m ? 0 : j + 1;
+            }
+            k = (c6 << kPosBits) | i;
         }
         s_key[kslot(i)] = k;
     }
     lds_sync();
     lds_bitonic_sort_reg(s_key, np);
 
-    for (uint32_t h = 4;; h <<= 1) {
+    for (uint32_t h = kKeyBytes;; h <<= 1) {
         // heads of groups in this thread's slots, then the group open before them
         unsigned long long prev = q0 ? s_key[kslot(q0 - 1)] : 0ull;
         uint32_t lasthead = 0, heads = 0;
