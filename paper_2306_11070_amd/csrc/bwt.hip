@@ -168,108 +168,191 @@ __device__ __forceinline__ uint32_t wg_sum(uint32_t v, uint32_t* s_red) {
 }  // namespace
 
 // ------------------------------------------------------------ forward
-// One workgroup per block of m <= 16384 bytes.  A key is
-// (group value << 14) | position: first the rotation's first six bytes, then,
-// once ranks exist, (rank, rank of the rotation h bytes further) -- so the
-// sorted keys order the rotations by their first 6, 12, 24, ... bytes, with
-// ties in start position.  Each round gives every rotation the slot of the
-// first key of its group as its rank, stops when all ranks differ (or when
-// h >= m: rotations still tied are equal and stay in start order), and
-// otherwise forms the next keys and sorts again with h doubled.  Each thread
-// owns a contiguous run of sort slots (and of positions).
+// One workgroup per block of m <= 16384 bytes, prefix doubling.  A key is
+// (group value << 14) | position: first the rotation's first six bytes, then
+// (rank, rank of the rotation h bytes further) -- so the sorted keys order the
+// rotations by their first 6, 12, 24, ... bytes, with ties in start
+// position.  After each sort every rotation's rank is the slot, in the order
+// of all rotations, of the first rotation of its group; it is kept by start
+// position (u16, in the upper part of the key array).  Rotations alone in
+// their group are placed for good; the next round sorts only the others once
+// they fit the lower part (at most kCompactMax), and each of their new ranks
+// is the old rank plus the offset of its new group inside the old one.  The
+// rounds stop when every group is alone, or when h >= m (rotations still tied
+// are equal and take their start order).  Each thread owns a contiguous run
+// of sort slots.
+constexpr uint32_t kCompactMax = HUFF_BWT_MAX_BLOCK / 2;
+constexpr uint32_t kRankSlot = kCompactMax + kCompactMax / 16;  // kslot(kCompactMax)
+static_assert(kRankSlot + HUFF_BWT_MAX_BLOCK * 2 / 8 <= kKeySlots, "the rank array fits above the compact keys");
+
+// Exclusive prefix sum of v over the threads of the workgroup, in thread order.
+__device__ __forceinline__ uint32_t wg_excl_sum(uint32_t v, uint32_t* s_red) {
+    const uint32_t lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= (uint32_t)d) x += y;
+    }
+    if (lane == 63) s_red[wave] = x;
+    lds_sync();
+    uint32_t before = 0;
+    for (uint32_t w = 0; w < wave; ++w) before += s_red[w];
+    lds_sync();
+    return before + x - v;
+}
+
 __global__ __launch_bounds__(kBwtThreads) void k_bwt(const uint8_t* __restrict__ in, uint64_t n, uint32_t block,
                                                      uint32_t every_log2, uint8_t* __restrict__ last,
                                                      uint16_t* __restrict__ rows) {
     __shared__ unsigned long long s_key[kKeySlots];
     __shared__ uint8_t s_blk[HUFF_BWT_MAX_BLOCK];
     __shared__ uint32_t s_red[kBwtThreads / 64];
+    uint16_t* s_rank = reinterpret_cast<uint16_t*>(s_key + kRankSlot);
     const uint32_t tid = threadIdx.x;
     const uint64_t lo = (uint64_t)blockIdx.x * block;
     const uint32_t m = (uint32_t)min<uint64_t>(block, n - lo);
     uint32_t np = 2 * kBwtThreads;
     while (np < m) np <<= 1;
-    const uint32_t per = np / kBwtThreads;
-    const uint32_t q0 = tid * per;
 
     for (uint32_t i = tid; i < m; i += kBwtThreads) s_blk[i] = in[lo + i];
     lds_sync();
-    for (uint32_t e = 0; e < per; ++e) {
-        const uint32_t i = q0 + e;
-        unsigned long long k = ~0ull;
-        if (i < m) {
-            unsigned long long c6 = 0;  // the rotation's first kKeyBytes bytes
-            uint32_t j = i;
+    {
+        const uint32_t per = np / kBwtThreads, q0 = tid * per;
+        for (uint32_t e = 0; e < per; ++e) {
+            const uint32_t i = q0 + e;
+            unsigned long long k = ~0ull;
+            if (i < m) {
+                unsigned long long c6 = 0;  // the rotation's first kKeyBytes bytes
+                uint32_t j = i;
 #pragma unroll
-            for (uint32_t t = 0; t < kKeyBytes; ++t) {
-                c6 = (c6 << 8) | s_blk[j];
-                j = j + 1 == m ? 0 : j + 1;
+                for (uint32_t t = 0; t < kKeyBytes; ++t) {
+                    c6 = (c6 << 8) | s_blk[j];
+                    j = j + 1 == m ? 0 : j + 1;
+                }
+                k = (c6 << kPosBits) | i;
             }
-            k = (c6 << kPosBits) | i;
+            s_key[kslot(i)] = k;
         }
-        s_key[kslot(i)] = k;
     }
     lds_sync();
     lds_bitonic_sort_reg(s_key, np);
 
+    uint32_t cnt = m, npc = np;  // sorted entries, and the sorted array's size
+    bool compact = false;        // the entries are the rotations still tied, keys (rank, rank h on, position)
     for (uint32_t h = kKeyBytes;; h <<= 1) {
-        // heads of groups in this thread's slots, then the group open before them
-        unsigned long long prev = q0 ? s_key[kslot(q0 - 1)] : 0ull;
-        uint32_t lasthead = 0, heads = 0;
+        const uint32_t per = npc / kBwtThreads, c0 = tid * per;
+        // group heads (same key but the position) and, in a compact round,
+        // old-group heads (same rank), up to this thread's slots
+        unsigned long long prev = c0 ? s_key[kslot(c0 - 1)] : 0ull;
+        uint32_t lastSub = 0, lastGrp = 0;
         for (uint32_t e = 0; e < per; ++e) {
-            const uint32_t q = q0 + e;
-            const unsigned long long k = s_key[kslot(q)];
-            if (q < m && (q == 0 || (k >> kPosBits) != (prev >> kPosBits))) {
-                lasthead = q;
-                ++heads;
+            const uint32_t c = c0 + e;
+            const unsigned long long k = s_key[kslot(c)];
+            if (c < cnt) {
+                if (c == 0 || (k >> kPosBits) != (prev >> kPosBits)) lastSub = c;
+                if (compact && (c == 0 || (k >> (2 * kPosBits)) != (prev >> (2 * kPosBits)))) lastGrp = c;
             }
             prev = k;
         }
-        const uint32_t open = wg_excl_max(lasthead, s_red);
-        if (wg_sum(heads, s_red) == m || h >= m) break;
-        uint32_t rank[kMaxPer], pos[kMaxPer];
-        uint32_t run = open;
-        prev = q0 ? s_key[kslot(q0 - 1)] : 0ull;
+        uint32_t sub = wg_excl_max(lastSub, s_red);
+        uint32_t grp = compact ? wg_excl_max(lastGrp, s_red) : 0u;
+        // new ranks (by start position) and the entries still tied
+        const bool final_ties = h >= m;
+        uint32_t pk[kMaxPer];  // position | new rank << 16
+        uint32_t heads = 0;    // bit e: entry e starts a group; bit per: the entry after the last starts one
+        prev = c0 ? s_key[kslot(c0 - 1)] : 0ull;
 #pragma unroll
         for (uint32_t e = 0; e < kMaxPer; ++e) {
-            rank[e] = pos[e] = 0;
+            pk[e] = 0;
             if (e < per) {
-                const uint32_t q = q0 + e;
-                const unsigned long long k = s_key[kslot(q)];
-                if (q < m && (q == 0 || (k >> kPosBits) != (prev >> kPosBits))) run = q;
-                rank[e] = run;
-                pos[e] = (uint32_t)(k & kPosMask);
+                const uint32_t c = c0 + e;
+                const unsigned long long k = s_key[kslot(c)];
+                if (c < cnt) {
+                    const bool sh = c == 0 || (k >> kPosBits) != (prev >> kPosBits);
+                    if (sh) sub = c;
+                    if (compact && (c == 0 || (k >> (2 * kPosBits)) != (prev >> (2 * kPosBits)))) grp = c;
+                    const uint32_t base = compact ? (uint32_t)(k >> (2 * kPosBits)) : 0u;
+                    const uint32_t r = base + (final_ties ? c : sub) - grp;
+                    pk[e] = (uint32_t)(k & kPosMask) | r << 16;
+                    heads |= (sh ? 1u : 0u) << e;
+                }
                 prev = k;
             }
         }
-        lds_sync();  // every sorted key has been read
-#pragma unroll
-        for (uint32_t e = 0; e < kMaxPer; ++e)
-            if (e < per && q0 + e < m) s_key[kslot(pos[e])] = rank[e];
-        lds_sync();
-        unsigned long long nk[kMaxPer];
+        {
+            // does the entry after this thread's last one start a group?
+            const uint32_t c = c0 + per;
+            const unsigned long long k = c < npc ? s_key[kslot(c)] : ~0ull;
+            if (c >= cnt || (k >> kPosBits) != (prev >> kPosBits)) heads |= 1u << per;
+        }
+        uint32_t tied = 0, ntied = 0;  // bit e: entry e shares its group
 #pragma unroll
         for (uint32_t e = 0; e < kMaxPer; ++e) {
-            const uint32_t i = q0 + e;
-            nk[e] = ~0ull;
-            if (e < per && i < m) {
-                const uint32_t j = i + h < m ? i + h : i + h - m;  // h < m here
-                nk[e] = (s_key[kslot(i)] << (2 * kPosBits)) | (s_key[kslot(j)] << kPosBits) | i;
+            if (e < per && c0 + e < cnt && !(((heads >> e) & 1u) && ((heads >> (e + 1)) & 1u))) {
+                tied |= 1u << e;
+                ++ntied;
             }
         }
-        lds_sync();
+        const uint32_t U = wg_sum(ntied, s_red);  // also: every sorted key has been read
 #pragma unroll
         for (uint32_t e = 0; e < kMaxPer; ++e)
-            if (e < per) s_key[kslot(q0 + e)] = nk[e];
+            if (e < per && c0 + e < cnt) s_rank[pk[e] & 0xffffu] = (uint16_t)(pk[e] >> 16);
         lds_sync();
-        lds_bitonic_sort_reg(s_key, np);
+        if (U == 0 || final_ties) break;
+        if (U <= kCompactMax) {
+            // the tied rotations' next keys, packed into the lower part
+            uint32_t c = wg_excl_sum(ntied, s_red);
+#pragma unroll
+            for (uint32_t e = 0; e < kMaxPer; ++e) {
+                if ((tied >> e) & 1u) {
+                    const uint32_t i = pk[e] & 0xffffu, r = pk[e] >> 16;
+                    const uint32_t j = i + h < m ? i + h : i + h - m;  // h < m here
+                    s_key[kslot(c)] = ((unsigned long long)r << (2 * kPosBits)) |
+                                      ((unsigned long long)s_rank[j] << kPosBits) | i;
+                    ++c;
+                }
+            }
+            npc = 2 * kBwtThreads;
+            while (npc < U) npc <<= 1;
+            for (uint32_t q = U + tid; q < npc; q += kBwtThreads) s_key[kslot(q)] = ~0ull;
+            cnt = U;
+            compact = true;
+        } else {
+            // every rotation's next key, in position order (before any compact round)
+            const uint32_t pf = np / kBwtThreads, q0 = tid * pf;
+            unsigned long long nk[kMaxPer];
+#pragma unroll
+            for (uint32_t e = 0; e < kMaxPer; ++e) {
+                const uint32_t i = q0 + e;
+                nk[e] = ~0ull;
+                if (e < pf && i < m) {
+                    const uint32_t j = i + h < m ? i + h : i + h - m;
+                    nk[e] = ((unsigned long long)s_rank[i] << (2 * kPosBits)) |
+                            ((unsigned long long)s_rank[j] << kPosBits) | i;
+                }
+            }
+            lds_sync();  // the ranks are read before the keys overwrite them
+#pragma unroll
+            for (uint32_t e = 0; e < kMaxPer; ++e)
+                if (e < pf) s_key[kslot(q0 + e)] = nk[e];
+            cnt = m;
+            npc = np;
+        }
+        lds_sync();
+        lds_bitonic_sort_reg(s_key, npc);
     }
 
-    // the last column, and the rows of the rotations starting at multiples of `every`
-    for (uint32_t q = tid; q < m; q += kBwtThreads) {
-        const uint32_t p = (uint32_t)(s_key[kslot(q)] & kPosMask);
-        last[lo + q] = s_blk[p ? p - 1 : m - 1];
-        if ((p & ((1u << every_log2) - 1)) == 0) rows[(lo + p) >> every_log2] = (uint16_t)q;
+    // s_rank[p]: the sorted row of the rotation starting at p.  The last
+    // column is put together in LDS (below the ranks) and stored in order.
+    uint8_t* s_out = reinterpret_cast<uint8_t*>(s_key);
+    for (uint32_t p = tid; p < m; p += kBwtThreads) {
+        const uint32_t r = s_rank[p];
+        s_out[r] = s_blk[p ? p - 1 : m - 1];
+        if ((p & ((1u << every_log2) - 1)) == 0) rows[(lo + p) >> every_log2] = (uint16_t)r;
     }
+    lds_sync();
+    for (uint32_t q = tid; q < m; q += kBwtThreads) last[lo + q] = s_out[q];
 }
 
 // ------------------------------------------------------- move to front
