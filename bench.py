@@ -663,6 +663,31 @@ def serve_leg(P, params: dict, seconds: float, pool_n: int, loads, chunk: int, s
     for r in base:
         srv.release(r["handle"])
     srv.close()
+    # the same request mix through a loop of plain calls (huff_compress or
+    # huff_decode per request, a host synchronisation after each)
+    codec = P.Codec(0, params)
+    streams = [codec.compress(x, chunk, sub) for x in pool]
+    torch.cuda.synchronize()
+    nloop = min(4000, 10 * pool_n)
+    k = rng.integers(0, pool_n, size=nloop)
+    comp = rng.random(nloop) < 0.7
+    moved = 0
+    t0 = time.perf_counter()
+    for i in range(nloop):
+        if comp[i]:
+            codec.compress(pool[k[i]], chunk, sub)
+        else:
+            codec.decompress(streams[k[i]])
+        torch.cuda.synchronize()
+        moved += sizes[k[i]]
+    loop_s = time.perf_counter() - t0
+    out["plain_loop"] = {"requests": nloop, "GBps": round(moved / loop_s / 1e9, 2),
+                         "what": "the same 70/30 request mix, one plain huff_compress or huff_decode call per request "
+                                 "with a host synchronisation after each"}
+    out["saturation_vs_plain_loop"] = round(out["saturation_GBps"] / (moved / loop_s / 1e9), 2)
+    del streams
+    codec.close()
+    progress(f"serve plain loop: {moved / loop_s / 1e9:.1f} GB/s")
     return out
 
 
