@@ -711,6 +711,12 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
         h.ntiles = b->ntiles;
         h.tile_hist = b->d_tile_hist;
         h.depth_log2 = log2u(c->params.hist_depth);
+        if (op == HUFF_OP_COMPRESS && b->d_file_hist) {
+            // every file's histogram, added up by the histogram launch
+            h.file_hist = b->d_file_hist;
+            huff_status st0 = hip_status(launch_fill_u64(b->d_file_hist, (uint64_t)b->nfiles * 256, 0, s));
+            if (st0 != HUFF_OK) return st0;
+        }
         uint64_t blocks = std::min<uint64_t>(c->params.hist_blocks, b->ntiles);
         const uint64_t tpb = (b->ntiles + blocks - 1) / blocks;
         h.tiles_per_block = tpb;
@@ -724,6 +730,7 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
         memset(&a, 0, sizeof(a));
         a.files = b->d_enc;
         a.tile_hist = b->d_tile_hist;
+        a.file_hist = b->ntiles > 0 ? b->d_file_hist : nullptr;
         a.err = c->status;
         huff_status st = hip_status(launch_codebook(a, b->nfiles, s));
         if (st != HUFF_OK) return st;
@@ -784,6 +791,7 @@ void batch_free(huff_batch* b) {
         (void)hipFree(b->d_tile_local);
         (void)hipFree(b->d_blk_tail);
         (void)hipFree(b->d_blk_carry);
+        (void)hipFree(b->d_file_hist);
     }
     delete b;
 }
@@ -818,7 +826,8 @@ huff_status huff_batch_create(huff_ctx* c, const huff_file* files, uint32_t nfil
               hipMalloc(&b->d_tile_file, std::max<uint64_t>(1, ntiles) * 4) == hipSuccess &&
               hipMalloc(&b->d_tile_hist, std::max<uint64_t>(1, ntiles) * 512) == hipSuccess &&
               hipMalloc(&b->d_tile_local, std::max<uint64_t>(1, ntiles) * 4) == hipSuccess &&
-              hipMalloc(&b->d_blk_tail, nblk * 8) == hipSuccess && hipMalloc(&b->d_blk_carry, nblk * 8) == hipSuccess;
+              hipMalloc(&b->d_blk_tail, nblk * 8) == hipSuccess && hipMalloc(&b->d_blk_carry, nblk * 8) == hipSuccess &&
+              hipMalloc(&b->d_file_hist, std::max<size_t>(1, nfiles) * 2048) == hipSuccess;
     if (!ok) { batch_free(b); return HUFF_E_NOMEM; }
     if ((nfiles && (hipMemcpy(b->d_enc, t.enc.data(), nfiles * sizeof(FileDesc), hipMemcpyHostToDevice) != hipSuccess ||
                     hipMemcpy(b->d_dec, t.dec.data(), nfiles * sizeof(FileDesc), hipMemcpyHostToDevice) != hipSuccess)) ||

@@ -114,11 +114,13 @@ struct HistArgs {
     uint16_t* tile_hist;    // optional per-16 KiB-tile histograms, [ntiles][256]
     uint32_t depth_log2;
     uint64_t tiles_per_block;
+    unsigned long long* file_hist;  // batch, optional: [nfiles][256] totals, added to (cleared by the caller)
 };
 
 struct CbArgs {
     const FileDesc* files;      // batch: one workgroup per file, histogram summed from ...
-    const uint16_t* tile_hist;  // ... the per-tile histograms; output into files[i].cb
+    const uint16_t* tile_hist;  // ... the per-tile histograms (or their totals, file_hist); output into files[i].cb
+    const unsigned long long* file_hist;  // batch, optional: [nfiles][256] histograms
     const uint64_t* hist;   // histogram input (from-histogram mode) ...
     HistState* acc;         // ... or the histogram accumulator, summed and zeroed here
     uint64_t* hist_out;     // optional copy of the summed histogram (accumulator mode)
@@ -138,6 +140,8 @@ struct CmpJob {
     const uint64_t* got_bits;
     uint64_t want_bits;
     int32_t* status;
+    uint32_t first_block;  // the job's first workgroup of the launch (set by launch_compare's caller)
+    uint32_t nblocks;      // and how many it has
 };
 
 // The fixed device workspace of huff_compress_noalloc (kernels.hip): byte
@@ -167,7 +171,9 @@ hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hip
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);
-hipError_t launch_compare(const CmpJob* jobs, uint32_t njobs, uint64_t total_bytes, hipStream_t s);
+// Workgroups a compare job of `bytes` bytes takes (first_block / nblocks).
+uint32_t compare_blocks(uint64_t bytes);
+hipError_t launch_compare(const CmpJob* jobs, uint32_t njobs, uint32_t total_blocks, hipStream_t s);
 // Method 3's block transform (bwt.hip).
 hipError_t launch_bwt(const uint8_t* in, uint64_t n, uint32_t block, uint32_t every_log2, uint8_t* last,
                       uint16_t* rows, hipStream_t s);

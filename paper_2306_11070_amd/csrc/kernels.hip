@@ -190,6 +190,7 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
     };
     unsigned long long total = 0;
     uint32_t run = 0, run2 = 0;  // with tile_hist: each set's sum for byte value tid after its previous tile
+    uint32_t curFile = 0xffffffffu;  // batch with file_hist: the file whose totals `total` holds
     const uint64_t off = (uint64_t)tid * 16;
     uint4 q0 = make_uint4(0, 0, 0, 0), q1 = q0;
     Src cur = {nullptr, 0, 0};
@@ -220,6 +221,17 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
                 const uint32_t c = s - (odd ? run2 : run);
                 a.tile_hist[t * 256 + tid] = (uint16_t)c;
                 if (odd) run2 = s; else run = s;
+                if constexpr (kBatch) {
+                    // a file's totals go out when its tiles in this run end
+                    if (a.file_hist) {
+                        const uint32_t fi = a.tile_file[t];
+                        if (fi != curFile) {
+                            if (curFile != 0xffffffffu && total) atomicAdd(&a.file_hist[curFile * 256ull + tid], total);
+                            total = 0;
+                            curFile = fi;
+                        }
+                    }
+                }
                 total += c;
             }
             // one set: no thread may count the next tile before every thread
@@ -236,6 +248,9 @@ __global__ __launch_bounds__(kHistThreads) void k_hist(HistArgs a) {
                 for (uint32_t r = 0; r < depth; ++r) total += sh[(tid << dl) | ((r + rot) & (depth - 1))];
         }
         if (tid < 256 && total) atomicAdd(&a.st->acc[blockIdx.x % kHistCopies][tid], total);
+    } else {
+        if (a.file_hist && tid < 256 && curFile != 0xffffffffu && total)
+            atomicAdd(&a.file_hist[curFile * 256ull + tid], total);
     }
 }
 
@@ -299,14 +314,18 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
             const FileDesc& f = a.files[blockIdx.x];
             d = const_cast<huff_dcb*>(f.cb);  // the batch builds the codebooks it then reads
             if (f.status) err = f.status;
-            const uint64_t t0 = f.first, t1 = f.first + (f.n + kEncTile - 1) / kEncTile;
-            uint64_t acc4[4] = {0, 0, 0, 0};
-            uint64_t t = t0;
-            for (; t + 4 <= t1; t += 4)
+            if (a.file_hist) {
+                h = a.file_hist[(uint64_t)blockIdx.x * 256 + v];  // summed by the histogram launch
+            } else {
+                const uint64_t t0 = f.first, t1 = f.first + (f.n + kEncTile - 1) / kEncTile;
+                uint64_t acc4[4] = {0, 0, 0, 0};
+                uint64_t t = t0;
+                for (; t + 4 <= t1; t += 4)
 #pragma unroll
-                for (int k = 0; k < 4; ++k) acc4[k] += a.tile_hist[(t + k) * 256 + v];
-            for (; t < t1; ++t) acc4[0] += a.tile_hist[t * 256 + v];
-            h = acc4[0] + acc4[1] + acc4[2] + acc4[3];
+                    for (int k = 0; k < 4; ++k) acc4[k] += a.tile_hist[(t + k) * 256 + v];
+                for (; t < t1; ++t) acc4[0] += a.tile_hist[t * 256 + v];
+                h = acc4[0] + acc4[1] + acc4[2] + acc4[3];
+            }
             if (f.hist) f.hist[v] = h;
             if (f.n == 0 && v == 0) {  // an empty file's offset index is [0]
                 f.chunk_off[0] = 0;
@@ -2236,32 +2255,42 @@ hipError_t scratch_address(int device, void** out) {
 // Result checks of the request server: every workgroup takes a share of
 // every job's bytes (16 bytes per lane at a time when both sides are
 // 16-byte aligned, single bytes otherwise).
-__global__ __launch_bounds__(256) void k_compare(const CmpJob* jobs, uint32_t njobs) {
-    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    const uint64_t me = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (uint32_t j = 0; j < njobs; ++j) {
-        const CmpJob c = jobs[j];
-        bool diff = false;
-        if (me == 0 && c.got_bits && *c.got_bits != c.want_bits) diff = true;
-        const bool vec = (((uintptr_t)c.got | (uintptr_t)c.want) & 15u) == 0;
-        const uint64_t nv = vec ? c.bytes >> 4 : 0;
-        const uint4* g4 = reinterpret_cast<const uint4*>(c.got);
-        const uint4* w4 = reinterpret_cast<const uint4*>(c.want);
-        for (uint64_t i = me; i < nv; i += stride) {
-            const uint4 a = g4[i], b = w4[i];
-            diff |= a.x != b.x || a.y != b.y || a.z != b.z || a.w != b.w;
-        }
-        for (uint64_t i = (nv << 4) + me; i < c.bytes; i += stride) diff |= c.got[i] != c.want[i];
-        if (diff) atomicMin(c.status, (int32_t)HUFF_E_MISMATCH);
-    }
+// Every job has its own run of workgroups (first_block, nblocks: about
+// kCmpBytesPerBlock bytes each), so all jobs of a batch are compared at once.
+constexpr uint64_t kCmpBytesPerBlock = 64 << 10;
+
+uint32_t compare_blocks(uint64_t bytes) {
+    const uint64_t b = (bytes + kCmpBytesPerBlock - 1) / kCmpBytesPerBlock;
+    return (uint32_t)(b < 1 ? 1 : b);
 }
 
-hipError_t launch_compare(const CmpJob* jobs, uint32_t njobs, uint64_t total_bytes, hipStream_t s) {
-    if (njobs == 0) return hipSuccess;
-    uint64_t blocks = (total_bytes / 16 + 255) / 256;
-    if (blocks > 2048) blocks = 2048;
-    if (blocks == 0) blocks = 1;
-    hipLaunchKernelGGL(k_compare, dim3((uint32_t)blocks), dim3(256), 0, s, jobs, njobs);
+__global__ __launch_bounds__(256) void k_compare(const CmpJob* jobs, uint32_t njobs) {
+    // this workgroup's job: the last whose first block is at most blockIdx.x
+    uint32_t lo = 0, hi = njobs - 1;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) >> 1;
+        if (jobs[mid].first_block <= blockIdx.x) lo = mid; else hi = mid - 1;
+    }
+    const CmpJob c = jobs[lo];
+    const uint64_t stride = (uint64_t)c.nblocks * blockDim.x;
+    const uint64_t me = (uint64_t)(blockIdx.x - c.first_block) * blockDim.x + threadIdx.x;
+    bool diff = false;
+    if (me == 0 && c.got_bits && *c.got_bits != c.want_bits) diff = true;
+    const bool vec = (((uintptr_t)c.got | (uintptr_t)c.want) & 15u) == 0;
+    const uint64_t nv = vec ? c.bytes >> 4 : 0;
+    const uint4* g4 = reinterpret_cast<const uint4*>(c.got);
+    const uint4* w4 = reinterpret_cast<const uint4*>(c.want);
+    for (uint64_t i = me; i < nv; i += stride) {
+        const uint4 a = g4[i], b = w4[i];
+        diff |= a.x != b.x || a.y != b.y || a.z != b.z || a.w != b.w;
+    }
+    for (uint64_t i = (nv << 4) + me; i < c.bytes; i += stride) diff |= c.got[i] != c.want[i];
+    if (diff) atomicMin(c.status, (int32_t)HUFF_E_MISMATCH);
+}
+
+hipError_t launch_compare(const CmpJob* jobs, uint32_t njobs, uint32_t total_blocks, hipStream_t s) {
+    if (njobs == 0 || total_blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_compare, dim3(total_blocks), dim3(256), 0, s, jobs, njobs);
     return hipGetLastError();
 }
 

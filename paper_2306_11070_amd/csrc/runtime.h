@@ -47,6 +47,7 @@ struct huff_batch {
     uint32_t* d_tile_local = nullptr;
     unsigned long long* d_blk_tail = nullptr;
     unsigned long long* d_blk_carry = nullptr;
+    unsigned long long* d_file_hist = nullptr;  // [nfiles][256] histogram totals of a compress
     hipStream_t cap = nullptr;   // capture stream
     hipGraph_t graph[3] = {nullptr, nullptr, nullptr};
     hipGraphExec_t exec[3] = {nullptr, nullptr, nullptr};

@@ -175,7 +175,7 @@ struct huff_server {
         return 2 * up(std::max<uint32_t>(nreq, 1) * sizeof(FileDesc), kAlign) + up(nreq * 4 + 8, kAlign) +
                up(nreq * 8 + 8, kAlign) + up(nreq * 8 + 8, kAlign) + up(std::max<uint64_t>(ntiles, 1) * 4, kAlign) +
                up(std::max<uint32_t>(nreq, 1) * sizeof(CmpJob), kAlign) +
-               up(batch_workspace_bytes(ntiles) + 4 * kAlign, kAlign);
+               up(batch_workspace_bytes(ntiles) + 4 * kAlign, kAlign) + up(std::max<uint32_t>(nreq, 1) * 2048, kAlign);
     }
 
     void run();
@@ -244,6 +244,7 @@ bool huff_server::launch(Slot& sl) {
     uint32_t* d_tile_file = (uint32_t*)carve(std::max<uint64_t>(ntiles, 1) * 4);
     CmpJob* d_jobs = (CmpJob*)carve(std::max<uint32_t>(nreq, 1) * sizeof(CmpJob));
     uint8_t* ws = carve(batch_workspace_bytes(ntiles) + 4 * kAlign);
+    unsigned long long* d_file_hist = (unsigned long long*)carve(std::max<uint32_t>(nreq, 1) * 2048);
     for (uint32_t i = 0; i < nreq; ++i) {
         Req* q = take[i];
         q->res.t_start = t0;
@@ -317,7 +318,7 @@ bool huff_server::launch(Slot& sl) {
     if (st == HUFF_OK) st = batch_tables(df.data(), (uint32_t)df.size(), cfg.chunk_size, cfg.sub_size, dt, true);
     // result checks of the requests that carry an expected result
     std::vector<CmpJob> jobs;
-    uint64_t cmp_bytes = 0;
+    uint32_t cmp_blocks = 0;
     for (uint32_t i = 0; i < nreq; ++i) {
         const Req* q = sl.reqs[i];
         if (!q->r.d_expect) continue;
@@ -337,7 +338,9 @@ bool huff_server::launch(Slot& sl) {
             j.got = rs.out;
             j.bytes = rs.n;
         }
-        cmp_bytes += j.bytes;
+        j.first_block = cmp_blocks;
+        j.nblocks = compare_blocks(j.bytes);
+        cmp_blocks += j.nblocks;
         jobs.push_back(j);
     }
     // staging: [enc | dec | status zeros | length pointers | tile_file | checks]
@@ -392,6 +395,7 @@ bool huff_server::launch(Slot& sl) {
         pc.d_blk_tail = (unsigned long long*)w;
         w += up(nblk * 8, kAlign);
         pc.d_blk_carry = (unsigned long long*)w;
+        pc.d_file_hist = d_file_hist;  // [nfiles][256] totals
         pd.nfiles = (uint32_t)df.size();
         pd.nitems = dt.nitems;
         pd.can_decode = dt.can_decode;
@@ -401,7 +405,7 @@ bool huff_server::launch(Slot& sl) {
         if (st == HUFF_OK && pc.nfiles) st = hip_status(launch_gather_u64(d_lenptr, d_len, pc.nfiles, s));
         if (st == HUFF_OK && pd.nfiles) st = batch_launch(&pd, HUFF_OP_DECODE, s);
         if (st == HUFF_OK && !jobs.empty())
-            st = hip_status(launch_compare(d_jobs, (uint32_t)jobs.size(), cmp_bytes, s));
+            st = hip_status(launch_compare(d_jobs, (uint32_t)jobs.size(), cmp_blocks, s));
         uint8_t* rb = (uint8_t*)sl.readback;
         if (st == HUFF_OK && hipMemcpyAsync(rb, d_status, nreq * 4, hipMemcpyDeviceToHost, s) != hipSuccess) st = HUFF_E_HIP;
         if (st == HUFF_OK && cf.size() &&
