@@ -678,6 +678,11 @@ huff_status batch_tables(const huff_file* files, uint32_t nfiles, uint32_t chunk
         const uint64_t t0 = t.enc[i].first, t1 = t0 + (files[i].n + kEncTile - 1) / kEncTile;
         for (uint64_t k = t0; k < t1; ++k) t.tile_file[k] = i;
     }
+    t.blk_file.resize(t.nitems / kDecBatchBlock);
+    for (uint32_t i = 0; i < nfiles; ++i) {
+        const uint64_t b1 = i + 1 < nfiles ? t.dec[i + 1].first : t.nitems;
+        for (uint64_t k = t.dec[i].first / kDecBatchBlock; k < b1 / kDecBatchBlock; ++k) t.blk_file[k] = i;
+    }
     return HUFF_OK;
 }
 
@@ -700,6 +705,7 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
         a.use_sub = b->sub_size ? 1 : 0;
         a.nitems = b->nitems;
         a.err = c->status;
+        a.blk_file = b->d_blk_file;
         return hip_status(launch_decode(a, kDecBatchBlock, true, s));
     }
     if (b->ntiles > 0) {
@@ -787,6 +793,7 @@ void batch_free(huff_batch* b) {
         (void)hipFree(b->d_enc);
         (void)hipFree(b->d_dec);
         (void)hipFree(b->d_tile_file);
+        (void)hipFree(b->d_blk_file);
         (void)hipFree(b->d_tile_hist);
         (void)hipFree(b->d_tile_local);
         (void)hipFree(b->d_blk_tail);
@@ -827,11 +834,14 @@ huff_status huff_batch_create(huff_ctx* c, const huff_file* files, uint32_t nfil
               hipMalloc(&b->d_tile_hist, std::max<uint64_t>(1, ntiles) * 512) == hipSuccess &&
               hipMalloc(&b->d_tile_local, std::max<uint64_t>(1, ntiles) * 4) == hipSuccess &&
               hipMalloc(&b->d_blk_tail, nblk * 8) == hipSuccess && hipMalloc(&b->d_blk_carry, nblk * 8) == hipSuccess &&
-              hipMalloc(&b->d_file_hist, std::max<size_t>(1, nfiles) * 2048) == hipSuccess;
+              hipMalloc(&b->d_file_hist, std::max<size_t>(1, nfiles) * 2048) == hipSuccess &&
+              hipMalloc(&b->d_blk_file, std::max<size_t>(1, t.blk_file.size()) * 4) == hipSuccess;
     if (!ok) { batch_free(b); return HUFF_E_NOMEM; }
     if ((nfiles && (hipMemcpy(b->d_enc, t.enc.data(), nfiles * sizeof(FileDesc), hipMemcpyHostToDevice) != hipSuccess ||
                     hipMemcpy(b->d_dec, t.dec.data(), nfiles * sizeof(FileDesc), hipMemcpyHostToDevice) != hipSuccess)) ||
-        (ntiles && hipMemcpy(b->d_tile_file, t.tile_file.data(), ntiles * 4, hipMemcpyHostToDevice) != hipSuccess)) {
+        (ntiles && hipMemcpy(b->d_tile_file, t.tile_file.data(), ntiles * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        (!t.blk_file.empty() &&
+         hipMemcpy(b->d_blk_file, t.blk_file.data(), t.blk_file.size() * 4, hipMemcpyHostToDevice) != hipSuccess)) {
         batch_free(b);
         return HUFF_E_HIP;
     }

@@ -102,6 +102,7 @@ struct DecArgs {
     uint32_t use_sub;       // 1: start bits from sub_lo, else from chunk_off
     uint64_t nitems;        // total lanes over all files (files padded to whole blocks)
     int32_t* err;
+    const uint32_t* blk_file;  // batch, optional: file of every block of 256 lanes (else a search over `files`)
 };
 
 struct HistArgs {

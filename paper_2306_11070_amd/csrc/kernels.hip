@@ -97,6 +97,12 @@ __device__ __forceinline__ uint32_t find_file(const FileDesc* files, uint32_t nf
     return lo;
 }
 
+// File of decode lane `item` of a batch (files start on a block of 256
+// lanes): one read of the block table when the plan has one.
+__device__ __forceinline__ uint32_t dec_file(const DecArgs& a, uint64_t item) {
+    return a.blk_file ? a.blk_file[item >> 8] : find_file(a.files, a.nfiles, item);
+}
+
 // ============================================================== histogram
 __device__ __forceinline__ uint32_t byte32(const uint4& x0, const uint4& x1, int i) {
     return i < 16 ? byte_of(x0, i) : byte_of(x1, i - 16);
@@ -1432,8 +1438,23 @@ struct DecTablesT {
 using DecTables = DecTablesT<HUFF_LUT_BITS>;
 // The longer-code decoders' table: 12-bit peeks, so that codes of 11 and 12
 // bits (most of the longer codes a byte alphabet gets) decode from the table.
+// Codes longer still decode from a second table.  In a canonical code the
+// longer codes take the largest values, so every code longer than 12 bits
+// starts with one of the last 12-bit prefixes, [P, 4096), where P counts the
+// prefixes the codes of at most 12 bits cover; the second table is indexed by
+// the maxLen-bit peek minus P << (maxLen - 12) and has
+// (4096 - P) << (maxLen - 12) entries, kept when at most kL2Max.
 constexpr uint32_t kWideLutBits = 12;
-using DecTablesWide = DecTablesT<kWideLutBits>;
+constexpr uint32_t kL2Max = 2048;
+struct DecTablesWide : DecTablesT<kWideLutBits> {
+    uint8_t len2[kL2Max];  // second table: code length (0: no code)
+    uint8_t sym2[kL2Max];  // second table: byte
+};
+// Where a lane finds the second-table entry of the 32 window bits `top`:
+// min((top >> sh) - base, last).
+struct L2Index {
+    uint32_t sh, base, last;
+};
 
 template <class Tab>
 __device__ __forceinline__ void load_tables(Tab& t, const huff_dcb* cb, uint32_t lutBits) {
@@ -1456,25 +1477,56 @@ __device__ __forceinline__ void load_tables(Tab& t, const huff_dcb* cb, uint32_t
 // the codebook's entry for its first lut_bits bits when that entry has a
 // code; otherwise the code starting with i is longer than lut_bits, and a
 // canonical search over the lengths up to wideBits finds it (0 if it is
-// longer still).  The canonical tables are loaded as by load_tables.
-__device__ __forceinline__ void load_tables_wide(DecTablesWide& t, const huff_dcb* cb, uint32_t wideBits,
-                                                 uint32_t maxLen) {
+// longer still).  For codes of 13 to 32 bits the second table is filled the
+// same way over the lengths past wideBits; the return value says where its
+// entries are, with last = 0 when it is not built (the code is too long, or
+// the table would pass kL2Max), so that such codes take the canonical search
+// at decode time.  The canonical tables are loaded as by load_tables.
+__device__ __forceinline__ L2Index load_tables_wide(DecTablesWide& t, const huff_dcb* cb, uint32_t wideBits,
+                                                    uint32_t maxLen) {
     const uint32_t lb = cb->lut_bits, sh = wideBits - lb;
-    for (uint32_t i = threadIdx.x; i < (1u << wideBits); i += blockDim.x) {
-        const uint32_t e = cb->lut[i >> sh];
-        uint32_t len = e >> 8, sym = e & 0xffu;
-        if (len == 0) {
-            for (uint32_t l = lb + 1; l <= wideBits && l <= maxLen; ++l) {
-                const uint64_t c = i >> (wideBits - l);
-                if (c - cb->first_code[l] < cb->count[l]) {
-                    sym = cb->sorted_sym[cb->first_index[l] + (uint32_t)(c - cb->first_code[l])];
-                    len = l;
-                    break;
+    const uint32_t lmax = min(wideBits, maxLen);
+    for (uint32_t j = threadIdx.x; j < (1u << lb); j += blockDim.x) {
+        const uint32_t e = cb->lut[j];
+        for (uint32_t r = 0; r < (1u << sh); ++r) {
+            const uint32_t i = (j << sh) | r;
+            uint32_t len = e >> 8, sym = e & 0xffu;
+            if (len == 0) {
+                for (uint32_t l = lb + 1; l <= lmax; ++l) {
+                    const uint64_t c = i >> (wideBits - l);
+                    if (c - cb->first_code[l] < cb->count[l]) {
+                        sym = cb->sorted_sym[cb->first_index[l] + (uint32_t)(c - cb->first_code[l])];
+                        len = l;
+                        break;
+                    }
                 }
             }
+            t.len8[i] = (uint8_t)len;
+            t.sym8[i] = (uint8_t)sym;
         }
-        t.len8[i] = (uint8_t)len;
-        t.sym8[i] = (uint8_t)sym;
+    }
+    L2Index l2 = {0u, 0u, 0u};
+    if (wideBits == kWideLutBits && maxLen > wideBits && maxLen <= 32) {
+        const uint64_t P = cb->first_code[wideBits] + cb->count[wideBits];
+        const uint32_t extra = maxLen - wideBits;
+        const uint64_t n2 = P < (1ull << wideBits) ? ((1ull << wideBits) - P) << extra : 0ull;
+        if (n2 > 0 && n2 <= kL2Max) {
+            const uint64_t base = P << extra;  // maxLen-bit value of the second table's entry 0
+            for (uint32_t i = threadIdx.x; i < (uint32_t)n2; i += blockDim.x) {
+                uint32_t len = 0, sym = 0;
+                for (uint32_t l = wideBits + 1; l <= maxLen; ++l) {
+                    const uint64_t c = (base + i) >> (maxLen - l);
+                    if (c - cb->first_code[l] < cb->count[l]) {
+                        sym = cb->sorted_sym[cb->first_index[l] + (uint32_t)(c - cb->first_code[l])];
+                        len = l;
+                        break;
+                    }
+                }
+                t.len2[i] = (uint8_t)len;
+                t.sym2[i] = (uint8_t)sym;
+            }
+            l2 = {32u - maxLen, (uint32_t)base, (uint32_t)n2 - 1u};
+        }
     }
     for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
         t.first[i] = cb->first_code[i];
@@ -1482,6 +1534,7 @@ __device__ __forceinline__ void load_tables_wide(DecTablesWide& t, const huff_dc
         t.fidx[i] = cb->first_index[i];
     }
     for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) t.sorted[i] = cb->sorted_sym[i];
+    return l2;
 }
 
 // Codes longer than the table: canonical search on the top 32 window bits.
@@ -1563,6 +1616,32 @@ struct WinReader {
         cons += len;
         ++c;
         return t.sym8[idx];
+    }
+    // The same with the second table for codes past the wide peek table
+    // (k * maxLen <= 33, so that the window still holds maxLen bits at the
+    // last of its k codes).
+    __device__ __forceinline__ uint32_t next2(const DecTablesWide& t, uint32_t lutBits, const L2Index& l2,
+                                              uint32_t& emin) {
+        if (c == k) {
+            pos += cons;
+            const uint32_t w = min(pos >> 5, last - 1);
+            win = (((uint64_t)s[w] << 32) | s[w + 1]) << (pos & 31);
+            cons = 0;
+            c = 0;
+        }
+        const uint32_t top = (uint32_t)(win >> 32);
+        const uint32_t idx = top >> (32 - lutBits);
+        uint32_t len = t.len8[idx], sym = t.sym8[idx];
+        if (len == 0) {
+            const uint32_t i2 = min((top >> l2.sh) - l2.base, l2.last);
+            len = t.len2[i2];
+            sym = t.sym2[i2];
+        }
+        emin = min(emin, len);
+        win <<= len;
+        cons += len;
+        ++c;
+        return sym;
     }
 };
 
@@ -1707,7 +1786,7 @@ __global__ __launch_bounds__(256) void k_decode(DecArgs a) {
     __shared__ DecTables t;
     const uint64_t item = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     FileDesc f;
-    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, (uint64_t)blockIdx.x * blockDim.x)];
+    if constexpr (kBatch) f = a.files[dec_file(a, (uint64_t)blockIdx.x * blockDim.x)];
     else f = a.one;
     const huff_dcb* cb = f.cb;
     const uint32_t lutBits = cb->lut_bits, maxLen = cb->max_len;
@@ -1760,13 +1839,14 @@ struct LenCmp {
 // (K - 1) * maxLen + lutBits <= 33.  NC = 0: lengths from the length table
 // (a length of 0, no code, is kept in emin); NC = 3: the same for a complete
 // code, where every table entry has a code and nothing is kept; NC = 1 or 2:
-// lengths from NC comparisons (LenCmp).  Each byte is packed as soon as it is decoded, so the
-// table entries do not stay live.  pos: bit position in the buffer, advanced
-// past the S codes.
+// lengths from NC comparisons (LenCmp); NC = 4: codes longer than the wide
+// peek table from its second table (`l2`), with K * maxLen <= 33.  Each byte is packed as soon as it is
+// decoded, so the table entries do not stay live.  pos: bit position in the
+// buffer, advanced past the S codes.
 template <int S, int K, int NC, class Tab>
 __device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, uint32_t& pos, const Tab& t,
                                               uint32_t lutBits, const LenCmp lc, uint4 (&o)[S / 16],
-                                              uint32_t& emin) {
+                                              uint32_t& emin, const L2Index l2 = {0u, 0u, 0u}) {
     uint64_t win = 0;
     uint32_t cons = 0;
 #pragma unroll
@@ -1783,7 +1863,21 @@ __device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, 
             const uint32_t top = (uint32_t)(win >> 32);
             const uint32_t idx = top >> (32 - lutBits);
             uint32_t len;
-            if constexpr (NC == 0) {
+            if constexpr (NC == 4) {
+                len = t.len8[idx];
+                uint32_t sym = t.sym8[idx];
+                if (len == 0) {
+                    const uint32_t i2 = min((top >> l2.sh) - l2.base, l2.last);
+                    len = t.len2[i2];
+                    sym = t.sym2[i2];
+                }
+                emin = min(emin, len);
+                win <<= len;
+                cons += len;
+                w[i >> 2] |= sym << (8 * (i & 3));
+                if ((i & 3) == 3) asm volatile("" : "+v"(w[i >> 2]), "+v"(emin));
+                continue;
+            } else if constexpr (NC == 0) {
                 len = t.len8[idx];
                 emin = min(emin, len);
             } else if constexpr (NC == 3) {
@@ -1905,7 +1999,7 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
     auto& t = sm.t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     FileDesc f;
-    if constexpr (kBatch) f = a.files[find_file(a.files, a.nfiles, blk * 256)];
+    if constexpr (kBatch) f = a.files[dec_file(a, blk * 256)];
     else f = a.one;
     const huff_dcb* cb = f.cb;
     const uint32_t cbBits = cb->lut_bits, maxLen = cb->max_len;
@@ -1917,13 +2011,15 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
     // the longer-code launch peeks up to kWideLutBits bits: codes that fit
     // them decode from the table alone, like the first launch's
     uint32_t lutBits = cbBits;
+    L2Index l2 = {0u, 0u, 0u};
     if constexpr (kMode == kDecLong) {
         lutBits = min(maxLen, kWideLutBits);
-        load_tables_wide(t, cb, lutBits, maxLen);
+        l2 = load_tables_wide(t, cb, lutBits, maxLen);
     } else {
         load_tables(t, cb, lutBits);
     }
     const bool fits = maxLen <= lutBits;
+    const bool two = !fits && l2.last != 0;  // longer codes from the second table (the table has >= 2 entries)
 
     const uint64_t n = f.n;
     const uint64_t nitems = (n + S - 1) / S;
@@ -2031,6 +2127,33 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
                     used = rd.pos + rd.cons - bit0;
                 }
                 if (emin == 0u) bad = true;
+            } else if (two) {
+                if constexpr (kMode == kDecLong) {
+                    const uint32_t k2 = 33u / maxLen;  // codes a re-read window covers: 1 or 2
+                    uint32_t emin = 0xffffffffu;
+                    if (nsym == S) {
+                        uint4 o[G];
+                        uint32_t pos = bit0;
+                        const LenCmp lc = {0u, 0u, 0u};
+                        if (k2 >= 2) dec_lane_fits<S, 2, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, lc, o, emin, l2);
+                        else dec_lane_fits<S, 1, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, lc, o, emin, l2);
+                        used = pos - bit0;
+                        if ((j0 + 64) * S <= n) {
+                            wave_store<S>(o, s_in[wave], f.out + j0 * S, lane);
+                        } else {
+                            uint4* o4 = reinterpret_cast<uint4*>(f.out + j * S);
+#pragma unroll
+                            for (uint32_t g = 0; g < G; ++g) o4[g] = o[g];
+                        }
+                    } else {
+                        WinReader rd;
+                        rd.init(s_in[wave], kInWords, bit0, k2);
+                        uint8_t* out = f.out + j * S;
+                        for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)rd.next2(t, lutBits, l2, emin);
+                        used = rd.pos + rd.cons - bit0;
+                    }
+                    if (emin == 0u) bad = true;
+                }
             } else {
                 LdsReader rd;
                 rd.init(s_in[wave], kInWords, bit0);
@@ -2060,6 +2183,14 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
                 for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)rd.next(t, lutBits, emin);
                 if (emin == 0u) bad = true;
                 used = rd.pos + rd.cons - bit0;
+            } else if (two) {
+                if constexpr (kMode == kDecLong) {
+                    WinReader rd;
+                    rd.init(s_in[wave], kInWords, bit0, 33u / maxLen);
+                    for (uint32_t i = 0; i < nsym; ++i) out[i] = (uint8_t)rd.next2(t, lutBits, l2, emin);
+                    if (emin == 0u) bad = true;
+                    used = rd.pos + rd.cons - bit0;
+                }
             } else {
                 LdsReader rd;
                 rd.init(s_in[wave], kInWords, bit0);
@@ -2089,9 +2220,10 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
 
 // The longer-code launch of one stream below 128 bytes: workgroup b takes blocks b,
 // b + grid, ...  (kept apart from k_decode_lds: the loop costs the
-// table-only path registers, about 64 -> 107 VGPRs at 64 bytes).
+// table-only path registers, about 64 -> 124 VGPRs at 64 bytes, held to
+// four waves per SIMD).
 template <int S, bool kBatch>
-__global__ __launch_bounds__(256) void k_decode_lds_long(DecArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_decode_lds_long(DecArgs a) {
     __shared__ StagedLdsFor<S, kDecLong> sm;
     const uint64_t nblk = (a.nitems + 255) / 256;
     for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {

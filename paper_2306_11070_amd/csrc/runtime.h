@@ -43,6 +43,7 @@ struct huff_batch {
     huff::FileDesc* d_enc = nullptr;   // [nfiles], first = first tile
     huff::FileDesc* d_dec = nullptr;   // [nfiles], first = first decode lane (256-aligned)
     uint32_t* d_tile_file = nullptr;
+    uint32_t* d_blk_file = nullptr;    // [nitems / kDecBatchBlock] decode block -> file, or null (search)
     uint16_t* d_tile_hist = nullptr;
     uint32_t* d_tile_local = nullptr;
     unsigned long long* d_blk_tail = nullptr;
@@ -83,6 +84,7 @@ struct BatchTables {
     std::vector<FileDesc> enc;       // first = first tile of the file
     std::vector<FileDesc> dec;       // first = first decode lane (kDecBatchBlock-aligned)
     std::vector<uint32_t> tile_file; // tile -> file
+    std::vector<uint32_t> blk_file;  // block of kDecBatchBlock decode lanes -> file
     uint64_t ntiles = 0, nitems = 0;
     bool aligned = true;             // every input 16-byte aligned
     bool can_decode = true;          // every non-empty file has an output buffer

@@ -259,10 +259,12 @@ def test_batch_scan_carries_across_blocks(P, codec):
 
 
 def test_batch_codes_past_the_table(P, codec):
-    """Files whose longest codes are 9, 11, 12, 13 and 15 bits in one batch:
-    the longer-code decode launch takes the files past the 10-bit table and
-    decodes codes of up to 12 bits from its 12-bit table.  Every file against
-    the oracle alone, and decoded back."""
+    """Files whose longest codes are 9, 11, 12, 13 and 15 bits in one batch,
+    and Zipf files with 14-, 17- and 20-bit codes: the longer-code decode
+    launch takes the files past the 10-bit table, decodes codes of up to 12
+    bits from its 12-bit table and longer ones from its second table, or by
+    canonical search where that table would pass its capacity (the 20-bit
+    file).  Every file against the oracle alone, and decoded back."""
     data = []
     for i, L in enumerate([9, 11, 12, 13, 15, 11]):
         M = (1 << 19) >> L
@@ -270,6 +272,10 @@ def test_batch_codes_past_the_table(P, codec):
         a = np.repeat((np.arange(L + 1) * 11 + 1).astype(np.uint8), counts)
         np.random.default_rng(40 + i).shuffle(a)
         data.append(a[: a.size - 3 * i])  # ragged ends
+    for i, s in enumerate([1.6, 2.0, 2.2]):
+        data.append(datagen.zipf_iid((1 << 20) + 5 * i, 3, s, datagen.A256))
+    want = [9, 11, 12, 13, 15, 11, 14, 17, 20]
+    assert [int(oracle.code_lengths(np.bincount(a, minlength=256)).max()) for a in data] == want
     _say(f"batch past the table: {len(data)} files")
     for sub in (32, 64):
         chunk = 16384

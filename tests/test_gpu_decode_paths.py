@@ -119,11 +119,41 @@ def _dyadic(L, seed):
 def test_staged_wide_table(codec, sub, L):
     """Codes just past the 10-bit table: the longer-code launch peeks 12 bits,
     so 11- and 12-bit codes decode from its table (two or three codes per
-    window), 13 bits and more by canonical search."""
+    window), 13 bits and more from its second table."""
     _say(f"staged wide table sub={sub} L={L}")
     a = _dyadic(L, seed=L)
     r = oracle.compress(a, 4096, sub=sub)
     assert int(oracle.code_lengths(r["hist"]).max()) == L
+    _roundtrip(codec, a, 4096, sub)
+
+
+WIDE_BITS, L2_MAX = 12, 2048  # the longer-code launch's peek bits and second-table capacity
+
+
+def _second_table_entries(lengths):
+    """Entries of the second table of a code (codes longer than WIDE_BITS bits):
+    the WIDE_BITS-bit prefixes that the longer codes take, times 2^(maxLen - WIDE_BITS)."""
+    ln = np.asarray(lengths)
+    L = int(ln.max())
+    if L <= WIDE_BITS:
+        return 0
+    cnt = np.bincount(ln[ln > 0], minlength=64)
+    covered = sum(int(cnt[l]) << (WIDE_BITS - l) for l in range(1, WIDE_BITS + 1))
+    return ((1 << WIDE_BITS) - covered) << (L - WIDE_BITS)
+
+
+@pytest.mark.parametrize("s,max_len,table", [(1.6, 14, True), (1.8, 15, True), (2.0, 17, True), (2.2, 20, False)])
+@pytest.mark.parametrize("sub", [32, 64])
+def test_staged_second_table(codec, sub, s, max_len, table):
+    """Codes past the 12-bit peek table: from the second table, two codes per
+    window up to 16 bits and one past that, or by canonical search when the
+    second table would pass its capacity; a ragged tail ends the stream."""
+    _say(f"staged second table sub={sub} s={s}")
+    a = datagen.zipf_iid((1 << 20) + 17, 3, s, datagen.A256)
+    r = oracle.compress(a, 4096, sub=sub)
+    ln = oracle.code_lengths(r["hist"])
+    assert int(ln.max()) == max_len
+    assert (0 < _second_table_entries(ln) <= L2_MAX) == table
     _roundtrip(codec, a, 4096, sub)
 
 
