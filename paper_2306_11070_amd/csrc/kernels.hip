@@ -1832,15 +1832,14 @@ struct LenCmp {
 
 // S symbols of one lane's sub-block into registers, 16 per uint4 in stream
 // order, for codes that all fit the peek table.  The 64 stream bits at the
-// position are re-read from LDS every K symbols, at positions fixed at
-// compile time, so the unrolled run has no branch: a window read at most 31
-// bits into a word holds at least 33 bits ahead, enough for K codes of at
-// most maxLen bits and the peek of the last when
-// (K - 1) * maxLen + lutBits <= 33.  NC = 0: lengths from the length table
+// position are re-read from LDS (three words, shifted) every K symbols, at
+// positions fixed at compile time, so the unrolled run has no branch: the
+// window holds 64 bits ahead, enough for K codes of at most maxLen bits and
+// the peek of the last when (K - 1) * maxLen + lutBits <= 64.  NC = 0: lengths from the length table
 // (a length of 0, no code, is kept in emin); NC = 3: the same for a complete
 // code, where every table entry has a code and nothing is kept; NC = 1 or 2:
 // lengths from NC comparisons (LenCmp); NC = 4: codes longer than the wide
-// peek table from its second table (`l2`), with K * maxLen <= 33.  Each byte is packed as soon as it is
+// peek table from its second table (`l2`), with K * maxLen <= 64.  Each byte is packed as soon as it is
 // decoded, so the table entries do not stay live.  pos: bit position in the
 // buffer, advanced past the S codes.
 template <int S, int K, int NC, class Tab>
@@ -1856,8 +1855,8 @@ __device__ __forceinline__ void dec_lane_fits(const uint32_t* s, uint32_t last, 
         for (uint32_t i = 0; i < 16; ++i) {
             if ((g * 16 + i) % K == 0) {
                 pos += cons;
-                const uint32_t wi = min(pos >> 5, last - 1);
-                win = (((uint64_t)s[wi] << 32) | s[wi + 1]) << (pos & 31);
+                const uint32_t wi = min(pos >> 5, last - 2), sh = pos & 31;
+                win = ((((uint64_t)s[wi] << 32) | s[wi + 1]) << sh) | (((uint64_t)s[wi + 2] << sh) >> 32);
                 cons = 0;
             }
             const uint32_t top = (uint32_t)(win >> 32);
@@ -2065,7 +2064,8 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
         if (active && !direct) {
             const uint32_t bit0 = (uint32_t)(start - (base << 5));
             if (fits) {
-                const uint32_t k = (33u - lutBits) / maxLen + 1;  // symbols a re-read window covers
+                const uint32_t k = (33u - lutBits) / maxLen + 1;  // symbols a re-read 33-bit window covers
+                const uint32_t k64 = (64u - lutBits) / maxLen + 1;  // ... and a 64-bit one
                 uint32_t emin = 0xffffffffu;
                 if (nsym == S) {
                     uint4 o[G];
@@ -2092,24 +2092,21 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
                     }
                     uint32_t* sb = s_in[wave];
                     if (cmp && span == 2) {
-                        if (k >= 8) dec_lane_fits<S, 8, 2>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        if (k64 >= 8) dec_lane_fits<S, 8, 2>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                         else dec_lane_fits<S, 4, 2>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     } else if (cmp) {
-                        if (k >= 8) dec_lane_fits<S, 8, 1>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        if (k64 >= 8) dec_lane_fits<S, 8, 1>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                         else dec_lane_fits<S, 4, 1>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     } else if (complete) {
-                        if (k >= 8) dec_lane_fits<S, 8, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
-                        else if (k >= 4) dec_lane_fits<S, 4, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
-                        else if (k >= 3) dec_lane_fits<S, 3, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
-                        else dec_lane_fits<S, 2, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
-                    } else if (k >= 8) {
+                        if (k64 >= 8) dec_lane_fits<S, 8, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        else if (k64 >= 6) dec_lane_fits<S, 6, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        else dec_lane_fits<S, 4, 3>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    } else if (k64 >= 8) {  // k64 >= 5 here: maxLen <= lutBits <= 12
                         dec_lane_fits<S, 8, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
-                    } else if (k >= 4) {
-                        dec_lane_fits<S, 4, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
-                    } else if (k >= 3) {
-                        dec_lane_fits<S, 3, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                    } else if (k64 >= 6) {
+                        dec_lane_fits<S, 6, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     } else {
-                        dec_lane_fits<S, 2, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
+                        dec_lane_fits<S, 4, 0>(sb, kInWords - 1, pos, t, lutBits, lc, o, emin);
                     }
                     used = pos - bit0;
                     if ((j0 + 64) * S <= n) {
@@ -2129,14 +2126,16 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
                 if (emin == 0u) bad = true;
             } else if (two) {
                 if constexpr (kMode == kDecLong) {
-                    const uint32_t k2 = 33u / maxLen;  // codes a re-read window covers: 1 or 2
+                    const uint32_t k2 = 33u / maxLen;  // codes a re-read 33-bit window covers: 1 or 2
+                    const uint32_t k64 = 64u / maxLen;  // ... and a 64-bit one: 2 to 4
                     uint32_t emin = 0xffffffffu;
                     if (nsym == S) {
                         uint4 o[G];
                         uint32_t pos = bit0;
                         const LenCmp lc = {0u, 0u, 0u};
-                        if (k2 >= 2) dec_lane_fits<S, 2, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, lc, o, emin, l2);
-                        else dec_lane_fits<S, 1, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, lc, o, emin, l2);
+                        if (k64 >= 4) dec_lane_fits<S, 4, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, lc, o, emin, l2);
+                        else if (k64 >= 3) dec_lane_fits<S, 3, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, lc, o, emin, l2);
+                        else dec_lane_fits<S, 2, 4>(s_in[wave], kInWords - 1, pos, t, lutBits, lc, o, emin, l2);
                         used = pos - bit0;
                         if ((j0 + 64) * S <= n) {
                             wave_store<S>(o, s_in[wave], f.out + j0 * S, lane);
