@@ -1427,7 +1427,7 @@ __device__ __forceinline__ uint64_t peek64(const uint32_t* w, uint64_t nwords, u
 // lookup needs no address scaling or field extraction and the length, which
 // the next lookup waits for, comes straight from its own load.
 template <uint32_t B>
-struct DecTablesT {
+struct alignas(16) DecTablesT {  // 16-byte aligned: the tables are filled with 4- to 16-byte stores
     static constexpr uint32_t kBits = B;
     uint8_t len8[1 << B];  // peek -> code length; 0: no code of at most lutBits bits
     uint8_t sym8[1 << B];  // peek -> byte
@@ -1456,13 +1456,32 @@ struct L2Index {
     uint32_t sh, base, last;
 };
 
+static_assert(offsetof(huff_dcb, lut) % 16 == 0, "the peek table is read with 8-byte loads");
+
+// Lengths (byte 1 of each u16 entry) and bytes (byte 0) of four peek-table
+// entries held in two words.
+__device__ __forceinline__ uint32_t lut_lens4(uint2 e) {
+    return ((e.x >> 8) & 0xffu) | ((e.x >> 24) << 8) | (((e.y >> 8) & 0xffu) << 16) | ((e.y >> 24) << 24);
+}
+__device__ __forceinline__ uint32_t lut_syms4(uint2 e) {
+    return (e.x & 0xffu) | (((e.x >> 16) & 0xffu) << 8) | ((e.y & 0xffu) << 16) | (((e.y >> 16) & 0xffu) << 24);
+}
+
 template <class Tab>
 __device__ __forceinline__ void load_tables(Tab& t, const huff_dcb* cb, uint32_t lutBits) {
     const uint32_t nl = 1u << min(lutBits, (uint32_t)HUFF_LUT_BITS);
-    for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
-        const uint32_t e = cb->lut[i];
-        t.len8[i] = (uint8_t)(e >> 8);
-        t.sym8[i] = (uint8_t)e;
+    if (nl == 4 * blockDim.x) {
+        // the full table: four entries per thread, one 8-byte load, one
+        // 4-byte store per table (the codebook's table starts 16-byte aligned)
+        const uint2 e = reinterpret_cast<const uint2*>(cb->lut)[threadIdx.x];
+        reinterpret_cast<uint32_t*>(t.len8)[threadIdx.x] = lut_lens4(e);
+        reinterpret_cast<uint32_t*>(t.sym8)[threadIdx.x] = lut_syms4(e);
+    } else {
+        for (uint32_t i = threadIdx.x; i < nl; i += blockDim.x) {
+            const uint32_t e = cb->lut[i];
+            t.len8[i] = (uint8_t)(e >> 8);
+            t.sym8[i] = (uint8_t)e;
+        }
     }
     for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
         t.first[i] = cb->first_code[i];
@@ -2224,6 +2243,12 @@ __global__ __launch_bounds__(256) void k_decode_lds(DecArgs a) {
 template <int S, bool kBatch>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_decode_lds_long(DecArgs a) {
     __shared__ StagedLdsFor<S, kDecLong> sm;
+    if constexpr (!kBatch) {
+        // one codebook: if its codes all fit the peek table, the first launch
+        // decodes every block (the check each block would make, made once)
+        const huff_dcb* cb = a.one.cb;
+        if (cb->max_len <= cb->lut_bits) return;
+    }
     const uint64_t nblk = (a.nitems + 255) / 256;
     for (uint64_t blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         dec_staged_block<S, kBatch, kDecLong>(a, blk, sm);
