@@ -897,63 +897,12 @@ __device__ __forceinline__ uint32_t byte64(const uint4& a, const uint4& b, const
 // into one 32-bit group (so G codes of at most 32/G bits) before the group is
 // appended to a 64-bit accumulator.  Every group stores the accumulator's
 // current top word and moves to the next slot word only once that word is
-// full, so there is no branch.  G = 4 reads 8-bit codes from a byte table
-// indexed by the input byte itself.  G = 1 handles a partial unit of nv bytes.
+// full, so there is no branch.  A byte's code and length come from one table
+// read: G = 4 (codes of at most 8 bits) from s_cl16 (code in the low byte,
+// length in the high byte), G <= 3 from s_cl32 (code in the low half, length
+// in the high half).  G = 1 handles a partial unit of nv bytes.
 template <int G>
 __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const uint4 x2, const uint4 x3,
-                                          const uint8_t* s_len, const uint8_t* s_code8, const uint16_t* s_code16,
-                                          uint32_t* slot, uint32_t& L, uint32_t& nwp, uint32_t nv = kEncUnit) {
-    uint64_t acc = 0;
-    uint32_t na = 0, wi = 0;
-    auto emit = [&]() {
-        const uint32_t sh = na >= 32 ? na - 32 : 0;
-        slot[wi * kSlotStride] = (uint32_t)(acc >> sh);
-        const uint32_t full = na >= 32 ? 1u : 0u;
-        wi += full;
-        na -= full << 5;
-    };
-    if constexpr (G == 1) {
-        for (uint32_t i = 0; i < nv; ++i) {
-            const uint32_t v = byte64(x0, x1, x2, x3, (int)i);
-            const uint32_t l = s_len[v];
-            acc = (acc << l) | s_code16[v];
-            na += l;
-            emit();
-        }
-    } else {
-#pragma unroll
-        for (int i0 = 0; i0 < kEncUnit; i0 += G) {
-            uint32_t g = 0, gl = 0;
-#pragma unroll
-            for (int k = 0; k < G; ++k) {
-                if (i0 + k < kEncUnit) {
-                    const uint32_t v = byte64(x0, x1, x2, x3, i0 + k);
-                    const uint32_t l = s_len[v];
-                    const uint32_t c = G == 4 ? (uint32_t)s_code8[v] : (uint32_t)s_code16[v];
-                    g = (g << l) | c;
-                    gl += l;
-                }
-            }
-            acc = (acc << gl) | g;
-            na += gl;
-            emit();
-        }
-    }
-    L = wi * 32 + na;
-    nwp = wi;
-    if (na) {
-        slot[wi * kSlotStride] = (uint32_t)(acc << (32 - na));
-        ++nwp;
-    }
-    slot[nwp * kSlotStride] = 0;
-}
-
-// The same for the compact kernel (codes of at most kEncCompactMaxLen bits),
-// whose code and length come from one table read: G = 4 from s_cl16 (code in
-// the low byte, length in the high byte), G <= 3 from s_cl32 (code in the low
-// half, length in the high half).
-template <int G>
-__device__ __forceinline__ void pack_unit_c(const uint4 x0, const uint4 x1, const uint4 x2, const uint4 x3,
                                             const uint16_t* s_cl16, const uint32_t* s_cl32, uint32_t* slot,
                                             uint32_t& L, uint32_t& nwp, uint32_t nv = kEncUnit) {
     uint64_t acc = 0;
@@ -1015,13 +964,11 @@ template <bool kBatch, bool kAligned, int kRows>
 __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
     constexpr bool kCompact = kRows < kSlotWords;
     __shared__ uint32_t s_slot[kRows * kSlotStride];  // private slots; tile bytes (generic path)
-    // the full kernel's code tables; the compact kernel's combined ones
-    // (each kernel declares the other's with one entry)
+    // code | length << 16 and (codes of at most 8 bits) code | length << 8 per
+    // byte value; the full kernel also keeps the whole codes for longer ones
     __shared__ unsigned long long s_code[kCompact ? 1 : 256];
-    __shared__ uint16_t s_code16[kCompact ? 1 : 256];
-    __shared__ uint8_t s_code8[kCompact ? 1 : 256];
-    __shared__ uint32_t s_cl32[kCompact ? 256 : 1];
-    __shared__ uint16_t s_cl16[kCompact ? 256 : 1];
+    __shared__ uint32_t s_cl32[256];
+    __shared__ uint16_t s_cl16[256];
     __shared__ uint8_t s_len[256];
     __shared__ uint32_t s_prev4[8];  // the 32 input bytes before the tile
     __shared__ uint32_t s_L[kEncThreads];
@@ -1133,14 +1080,9 @@ __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
                 const uint64_t c = f.cb->code[tid];
                 const uint32_t l = f.cb->len[tid];
                 s_len[tid] = (uint8_t)l;
-                if constexpr (kCompact) {
-                    s_cl32[tid] = (uint32_t)(c & 0xffffu) | l << 16;
-                    s_cl16[tid] = (uint16_t)((c & 0xffu) | l << 8);
-                } else {
-                    s_code[tid] = c;
-                    s_code16[tid] = (uint16_t)c;
-                    s_code8[tid] = (uint8_t)c;
-                }
+                s_cl32[tid] = (uint32_t)(c & 0xffffu) | l << 16;
+                s_cl16[tid] = (uint16_t)((c & 0xffu) | l << 8);
+                if constexpr (!kCompact) s_code[tid] = c;
             }
             loaded = f.cb;
             __syncthreads();
@@ -1156,27 +1098,17 @@ __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
                 uint4 z0 = x0, z1 = x1, z2 = x2, z3 = x3;
                 asm volatile("" : "+v"(z0.x), "+v"(z0.y), "+v"(z0.z), "+v"(z0.w), "+v"(z1.x), "+v"(z1.y), "+v"(z1.z), "+v"(z1.w)::"memory");
                 asm volatile("" : "+v"(z2.x), "+v"(z2.y), "+v"(z2.z), "+v"(z2.w), "+v"(z3.x), "+v"(z3.y), "+v"(z3.z), "+v"(z3.w)::"memory");
-                if constexpr (kCompact) {
-                    // codes of at most 10 bits: three or four per group
-                    if (group == 4) {
-                        pack_unit_c<4>(z0, z1, z2, z3, s_cl16, s_cl32, slot, L, nwp);
-                    } else {
-                        asm volatile("" : "+v"(z0.x), "+v"(z1.x), "+v"(z2.x), "+v"(z3.x)::"memory");
-                        pack_unit_c<3>(z0, z1, z2, z3, s_cl16, s_cl32, slot, L, nwp);
-                    }
-                } else if (group == 4) {
-                    pack_unit<4>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp);
-                } else if (group == 3) {
+                if (group == 4) {
+                    pack_unit<4>(z0, z1, z2, z3, s_cl16, s_cl32, slot, L, nwp);
+                } else if (kCompact || group == 3) {  // the compact kernel's codes: at most 10 bits
                     asm volatile("" : "+v"(z0.x), "+v"(z1.x), "+v"(z2.x), "+v"(z3.x)::"memory");
-                    pack_unit<3>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp);
+                    pack_unit<3>(z0, z1, z2, z3, s_cl16, s_cl32, slot, L, nwp);
                 } else {
                     asm volatile("" : "+v"(z0.y), "+v"(z1.y), "+v"(z2.y), "+v"(z3.y)::"memory");
-                    pack_unit<2>(z0, z1, z2, z3, s_len, s_code8, s_code16, slot, L, nwp);
+                    pack_unit<2>(z0, z1, z2, z3, s_cl16, s_cl32, slot, L, nwp);
                 }
-            } else if constexpr (kCompact) {
-                pack_unit_c<1>(x0, x1, x2, x3, s_cl16, s_cl32, slot, L, nwp, nv);
             } else {
-                pack_unit<1>(x0, x1, x2, x3, s_len, s_code8, s_code16, slot, L, nwp, nv);
+                pack_unit<1>(x0, x1, x2, x3, s_cl16, s_cl32, slot, L, nwp, nv);
             }
         } else {
             uint4* in4 = reinterpret_cast<uint4*>(s_slot) + 4 * tid;
