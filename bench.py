@@ -32,7 +32,7 @@ WORKLOADS = {
     "zipf256_1GiB": ("1 GiB i.i.d. Zipf(0.8) over 256 byte values (the leading 2^30 bytes of the 2 GiB Zipf "
                      "stream), global codebook", 1 << 20, 128),
     "markov_45MiB": ("45 MiB order-2 Markov text over 96 printable bytes (Zipf(1.0) rows, newline after N(70,15)), "
-                     "global codebook", 256 << 10, 128),
+                     "global codebook", 256 << 10, 64),
     "zipf96_1MiB": ("1 MiB i.i.d. Zipf(1.1) over 96 printable bytes", 64 << 10, 256),
 }
 # the 2 GiB streams stay off the GPU: a run of that case once ended in a GPU

@@ -358,11 +358,14 @@ def test_missing_symbol_reported(codec, P):
 
 
 # ------------------------------------------------------------ full workloads
-def test_paper_scale_markov_45MiB(codec):
-    """The 45 MiB order-2 Markov text, 256 KiB chunks: full bit-exact parity."""
-    _say("markov 45 MiB")
+@pytest.mark.parametrize("sub", [1024, 64])
+def test_paper_scale_markov_45MiB(codec, sub):
+    """The 45 MiB order-2 Markov text, 256 KiB chunks: full bit-exact parity,
+    with the direct decoder (1 KiB sub-blocks) and with the staged one at the
+    64-byte sub-blocks the bench times."""
+    _say(f"markov 45 MiB sub={sub}")
     a = datagen.workload("markov_45MiB")
-    _roundtrip(codec, a, 256 << 10, 1024)
+    _roundtrip(codec, a, 256 << 10, sub)
 
 
 def test_small_zipf_1MiB(codec):
