@@ -897,14 +897,15 @@ __device__ __forceinline__ uint32_t byte64(const uint4& a, const uint4& b, const
 // into one 32-bit group (so G codes of at most 32/G bits) before the group is
 // appended to a 64-bit accumulator.  Every group stores the accumulator's
 // current top word and moves to the next slot word only once that word is
-// full, so there is no branch.  A byte's code and length come from one table
-// read: G = 4 (codes of at most 8 bits) from s_cl16 (code in the low byte,
-// length in the high byte), G <= 3 from s_cl32 (code in the low half, length
-// in the high half).  G = 1 handles a partial unit of nv bytes.
+// full, so there is no branch.  G = 4 (codes of at most 8 bits) reads the
+// length and the code from two byte tables (s_len, s_code8: the lanes of a
+// wave then meet fewer LDS bank conflicts than in one 16-bit table); G <= 3
+// reads both from one table read of s_cl32 (code in the low half, length in
+// the high half).  G = 1 handles a partial unit of nv bytes.
 template <int G>
 __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const uint4 x2, const uint4 x3,
-                                            const uint16_t* s_cl16, const uint32_t* s_cl32, uint32_t* slot,
-                                            uint32_t& L, uint32_t& nwp, uint32_t nv = kEncUnit) {
+                                            const uint8_t* s_len, const uint8_t* s_code8, const uint32_t* s_cl32,
+                                            uint32_t* slot, uint32_t& L, uint32_t& nwp, uint32_t nv = kEncUnit) {
     uint64_t acc = 0;
     uint32_t na = 0, wi = 0;
     auto emit = [&]() {
@@ -932,9 +933,8 @@ __device__ __forceinline__ void pack_unit(const uint4 x0, const uint4 x1, const 
                     const uint32_t v = byte64(x0, x1, x2, x3, i0 + k);
                     uint32_t l, c;
                     if constexpr (G == 4) {
-                        const uint32_t e = s_cl16[v];
-                        l = e >> 8;
-                        c = e & 0xffu;
+                        l = s_len[v];
+                        c = s_code8[v];
                     } else {
                         const uint32_t e = s_cl32[v];
                         l = e >> 16;
@@ -964,11 +964,11 @@ template <bool kBatch, bool kAligned, int kRows>
 __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
     constexpr bool kCompact = kRows < kSlotWords;
     __shared__ uint32_t s_slot[kRows * kSlotStride];  // private slots; tile bytes (generic path)
-    // code | length << 16 and (codes of at most 8 bits) code | length << 8 per
+    // code | length << 16, and (codes of at most 8 bits) the code alone, per
     // byte value; the full kernel also keeps the whole codes for longer ones
     __shared__ unsigned long long s_code[kCompact ? 1 : 256];
     __shared__ uint32_t s_cl32[256];
-    __shared__ uint16_t s_cl16[256];
+    __shared__ uint8_t s_code8[256];
     __shared__ uint8_t s_len[256];
     __shared__ uint32_t s_prev4[8];  // the 32 input bytes before the tile
     __shared__ uint32_t s_L[kEncThreads];
@@ -1081,7 +1081,7 @@ __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
                 const uint32_t l = f.cb->len[tid];
                 s_len[tid] = (uint8_t)l;
                 s_cl32[tid] = (uint32_t)(c & 0xffffu) | l << 16;
-                s_cl16[tid] = (uint16_t)((c & 0xffu) | l << 8);
+                s_code8[tid] = (uint8_t)c;
                 if constexpr (!kCompact) s_code[tid] = c;
             }
             loaded = f.cb;
@@ -1099,16 +1099,16 @@ __device__ __forceinline__ void encode_tiles(const EncArgs& a) {
                 asm volatile("" : "+v"(z0.x), "+v"(z0.y), "+v"(z0.z), "+v"(z0.w), "+v"(z1.x), "+v"(z1.y), "+v"(z1.z), "+v"(z1.w)::"memory");
                 asm volatile("" : "+v"(z2.x), "+v"(z2.y), "+v"(z2.z), "+v"(z2.w), "+v"(z3.x), "+v"(z3.y), "+v"(z3.z), "+v"(z3.w)::"memory");
                 if (group == 4) {
-                    pack_unit<4>(z0, z1, z2, z3, s_cl16, s_cl32, slot, L, nwp);
+                    pack_unit<4>(z0, z1, z2, z3, s_len, s_code8, s_cl32, slot, L, nwp);
                 } else if (kCompact || group == 3) {  // the compact kernel's codes: at most 10 bits
                     asm volatile("" : "+v"(z0.x), "+v"(z1.x), "+v"(z2.x), "+v"(z3.x)::"memory");
-                    pack_unit<3>(z0, z1, z2, z3, s_cl16, s_cl32, slot, L, nwp);
+                    pack_unit<3>(z0, z1, z2, z3, s_len, s_code8, s_cl32, slot, L, nwp);
                 } else {
                     asm volatile("" : "+v"(z0.y), "+v"(z1.y), "+v"(z2.y), "+v"(z3.y)::"memory");
-                    pack_unit<2>(z0, z1, z2, z3, s_cl16, s_cl32, slot, L, nwp);
+                    pack_unit<2>(z0, z1, z2, z3, s_len, s_code8, s_cl32, slot, L, nwp);
                 }
             } else {
-                pack_unit<1>(x0, x1, x2, x3, s_cl16, s_cl32, slot, L, nwp, nv);
+                pack_unit<1>(x0, x1, x2, x3, s_len, s_code8, s_cl32, slot, L, nwp, nv);
             }
         } else {
             uint4* in4 = reinterpret_cast<uint4*>(s_slot) + 4 * tid;
