@@ -1519,25 +1519,47 @@ __device__ __forceinline__ void load_tables(Tab& t, const huff_dcb* cb, uint32_t
 // at decode time.  The canonical tables are loaded as by load_tables.
 __device__ __forceinline__ L2Index load_tables_wide(DecTablesWide& t, const huff_dcb* cb, uint32_t wideBits,
                                                     uint32_t maxLen) {
+    // the canonical tables first, and the codebook's peek entries into
+    // registers: after one barrier the searches below read LDS, not memory
     const uint32_t lb = cb->lut_bits, sh = wideBits - lb;
     const uint32_t lmax = min(wideBits, maxLen);
-    for (uint32_t j = threadIdx.x; j < (1u << lb); j += blockDim.x) {
-        const uint32_t e = cb->lut[j];
-        for (uint32_t r = 0; r < (1u << sh); ++r) {
-            const uint32_t i = (j << sh) | r;
-            uint32_t len = e >> 8, sym = e & 0xffu;
-            if (len == 0) {
-                for (uint32_t l = lb + 1; l <= lmax; ++l) {
-                    const uint64_t c = i >> (wideBits - l);
-                    if (c - cb->first_code[l] < cb->count[l]) {
-                        sym = cb->sorted_sym[cb->first_index[l] + (uint32_t)(c - cb->first_code[l])];
-                        len = l;
-                        break;
-                    }
-                }
+    for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
+        t.first[i] = cb->first_code[i];
+        t.cnt[i] = cb->count[i];
+        t.fidx[i] = cb->first_index[i];
+    }
+    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) t.sorted[i] = cb->sorted_sym[i];
+    constexpr uint32_t kPer = (1u << HUFF_LUT_BITS) / 256;  // entries per thread (256-thread workgroups)
+    uint32_t ev[kPer];
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t j = threadIdx.x + 256 * k;
+        ev[k] = j < (1u << lb) ? cb->lut[j] : 0u;
+    }
+    __syncthreads();
+    auto search = [&](uint64_t code, uint32_t bits, uint32_t l0, uint32_t l1, uint32_t& len, uint32_t& sym) {
+        // the code of l0..l1 bits that the `bits`-bit value `code` starts with
+        for (uint32_t l = l0; l <= l1; ++l) {
+            const uint64_t c = code >> (bits - l);
+            if (c - t.first[l] < t.cnt[l]) {
+                sym = t.sorted[t.fidx[l] + (uint32_t)(c - t.first[l])];
+                len = l;
+                return;
             }
-            t.len8[i] = (uint8_t)len;
-            t.sym8[i] = (uint8_t)sym;
+        }
+    };
+#pragma unroll
+    for (uint32_t k = 0; k < kPer; ++k) {
+        const uint32_t j = threadIdx.x + 256 * k;
+        if (j < (1u << lb)) {
+            const uint32_t e = ev[k];
+            for (uint32_t r = 0; r < (1u << sh); ++r) {
+                const uint32_t i = (j << sh) | r;
+                uint32_t len = e >> 8, sym = e & 0xffu;
+                if (len == 0) search(i, wideBits, lb + 1, lmax, len, sym);
+                t.len8[i] = (uint8_t)len;
+                t.sym8[i] = (uint8_t)sym;
+            }
         }
     }
     L2Index l2 = {0u, 0u, 0u};
@@ -1549,26 +1571,13 @@ __device__ __forceinline__ L2Index load_tables_wide(DecTablesWide& t, const huff
             const uint64_t base = P << extra;  // maxLen-bit value of the second table's entry 0
             for (uint32_t i = threadIdx.x; i < (uint32_t)n2; i += blockDim.x) {
                 uint32_t len = 0, sym = 0;
-                for (uint32_t l = wideBits + 1; l <= maxLen; ++l) {
-                    const uint64_t c = (base + i) >> (maxLen - l);
-                    if (c - cb->first_code[l] < cb->count[l]) {
-                        sym = cb->sorted_sym[cb->first_index[l] + (uint32_t)(c - cb->first_code[l])];
-                        len = l;
-                        break;
-                    }
-                }
+                search(base + i, maxLen, wideBits + 1, maxLen, len, sym);
                 t.len2[i] = (uint8_t)len;
                 t.sym2[i] = (uint8_t)sym;
             }
             l2 = {32u - maxLen, (uint32_t)base, (uint32_t)n2 - 1u};
         }
     }
-    for (uint32_t i = threadIdx.x; i < 64; i += blockDim.x) {
-        t.first[i] = cb->first_code[i];
-        t.cnt[i] = cb->count[i];
-        t.fidx[i] = cb->first_index[i];
-    }
-    for (uint32_t i = threadIdx.x; i < 256; i += blockDim.x) t.sorted[i] = cb->sorted_sym[i];
     return l2;
 }
 
