@@ -371,8 +371,8 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
             uint32_t r0 = 0, r1 = 0;
             const ulonglong2* k2 = reinterpret_cast<const ulonglong2*>(s_tmp);
             uint32_t u = 0;
-#pragma unroll 4
-            for (; u < K / 2; ++u) {
+#pragma unroll 16
+            for (; u < K / 2; ++u) {  // independent broadcast reads: many in flight
                 const ulonglong2 p = k2[u];
                 r0 += p.x < key ? 1u : 0u;
                 r1 += p.y < key ? 1u : 0u;
@@ -588,7 +588,8 @@ __global__ __launch_bounds__(kCbThreads) void k_codebook(CbArgs a) {
             lo[l] = on ? (uint32_t)(s_first[l] << (lutBits - l)) : 0u;
             span[l] = on ? s_cnt[l] << (lutBits - l) : 0u;
         }
-        for (uint32_t p = v; p < (1u << HUFF_LUT_BITS); p += 256) {
+#pragma unroll
+        for (uint32_t p = v; p < (1u << HUFF_LUT_BITS); p += 256) {  // four independent entries in flight
             uint32_t len = 0;
 #pragma unroll
             for (uint32_t l = 1; l <= HUFF_LUT_BITS; ++l) len = p - lo[l] < span[l] ? l : len;
