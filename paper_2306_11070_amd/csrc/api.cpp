@@ -706,6 +706,14 @@ huff_status batch_launch(huff_batch* b, int op, hipStream_t s) {
         a.nitems = b->nitems;
         a.err = c->status;
         a.blk_file = b->d_blk_file;
+        if (b->d_blk_file && b->d_blk_mode) {
+            // which of the two staged launches takes each block, read by both
+            // with one load (the codebooks exist by now: built by a compress
+            // earlier on the stream, or given)
+            const hipError_t e = launch_blk_mode(b->d_blk_file, b->d_dec, b->d_blk_mode, b->nitems / kDecBatchBlock, s);
+            if (e != hipSuccess) return HUFF_E_HIP;
+            a.blk_mode = b->d_blk_mode;
+        }
         return hip_status(launch_decode(a, kDecBatchBlock, true, s));
     }
     if (b->ntiles > 0) {
@@ -794,6 +802,7 @@ void batch_free(huff_batch* b) {
         (void)hipFree(b->d_dec);
         (void)hipFree(b->d_tile_file);
         (void)hipFree(b->d_blk_file);
+        (void)hipFree(b->d_blk_mode);
         (void)hipFree(b->d_tile_hist);
         (void)hipFree(b->d_tile_local);
         (void)hipFree(b->d_blk_tail);
@@ -835,7 +844,8 @@ huff_status huff_batch_create(huff_ctx* c, const huff_file* files, uint32_t nfil
               hipMalloc(&b->d_tile_local, std::max<uint64_t>(1, ntiles) * 4) == hipSuccess &&
               hipMalloc(&b->d_blk_tail, nblk * 8) == hipSuccess && hipMalloc(&b->d_blk_carry, nblk * 8) == hipSuccess &&
               hipMalloc(&b->d_file_hist, std::max<size_t>(1, nfiles) * 2048) == hipSuccess &&
-              hipMalloc(&b->d_blk_file, std::max<size_t>(1, t.blk_file.size()) * 4) == hipSuccess;
+              hipMalloc(&b->d_blk_file, std::max<size_t>(1, t.blk_file.size()) * 4) == hipSuccess &&
+              hipMalloc(&b->d_blk_mode, std::max<size_t>(1, t.blk_file.size())) == hipSuccess;
     if (!ok) { batch_free(b); return HUFF_E_NOMEM; }
     if ((nfiles && (hipMemcpy(b->d_enc, t.enc.data(), nfiles * sizeof(FileDesc), hipMemcpyHostToDevice) != hipSuccess ||
                     hipMemcpy(b->d_dec, t.dec.data(), nfiles * sizeof(FileDesc), hipMemcpyHostToDevice) != hipSuccess)) ||

@@ -103,6 +103,7 @@ struct DecArgs {
     uint64_t nitems;        // total lanes over all files (files padded to whole blocks)
     int32_t* err;
     const uint32_t* blk_file;  // batch, optional: file of every block of 256 lanes (else a search over `files`)
+    const uint8_t* blk_mode;   // batch, optional: 1 where a block's codebook has codes past its peek table
 };
 
 struct HistArgs {
@@ -169,6 +170,9 @@ hipError_t launch_encode(const EncArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_encode_empty(uint64_t* chunk_off, uint32_t* sub_lo, hipStream_t s);
 // out_aligned: every output is 16-byte aligned (the staged decoder requires it)
 hipError_t launch_decode(const DecArgs& a, uint32_t block, bool out_aligned, hipStream_t s);
+// Fills mode[b] for the nblk decode blocks of a batch (from blk_file and the files' codebooks).
+hipError_t launch_blk_mode(const uint32_t* blk_file, const FileDesc* files, uint8_t* mode, uint64_t nblk,
+                           hipStream_t s);
 hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s);
 hipError_t launch_gather_u64(const uint64_t* const* src, uint64_t* dst, uint32_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, uint64_t count, unsigned long long v, hipStream_t s);

@@ -2043,8 +2043,13 @@ __device__ __forceinline__ void dec_staged_block(const DecArgs& a, uint64_t blk,
     auto& t = sm.t;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     FileDesc f;
-    if constexpr (kBatch) f = a.files[dec_file(a, blk * 256)];
-    else f = a.one;
+    if constexpr (kBatch) {
+        // the other launch's block: one load of its mode, no file or codebook reads
+        if (kMode != kDecBoth && a.blk_mode && (a.blk_mode[blk] != 0) != (kMode == kDecLong)) return;
+        f = a.files[dec_file(a, blk * 256)];
+    } else {
+        f = a.one;
+    }
     const huff_dcb* cb = f.cb;
     const uint32_t cbBits = cb->lut_bits, maxLen = cb->max_len;
     if (kMode != kDecBoth && (maxLen <= cbBits) != (kMode == kDecFits)) return;  // the other launch decodes this block
@@ -2373,6 +2378,22 @@ hipError_t launch_copy(const void* src, void* dst, uint64_t bytes, hipStream_t s
     uint64_t g = ((bytes >> 4) + kCopyChunk - 1) / kCopyChunk;
     if (g == 0) g = 1;
     hipLaunchKernelGGL(k_copy, dim3((uint32_t)g), dim3(256), 0, s, (const uint8_t*)src, (uint8_t*)dst, bytes);
+    return hipGetLastError();
+}
+
+// mode[b] = 1 when the codebook of decode block b's file has codes longer
+// than its peek table (the staged decoder's second launch takes the block).
+__global__ void k_blk_mode(const uint32_t* blk_file, const FileDesc* files, uint8_t* mode, uint64_t nblk) {
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nblk) return;
+    const huff_dcb* cb = files[blk_file[b]].cb;
+    mode[b] = cb->max_len > cb->lut_bits ? 1u : 0u;
+}
+
+hipError_t launch_blk_mode(const uint32_t* blk_file, const FileDesc* files, uint8_t* mode, uint64_t nblk,
+                           hipStream_t s) {
+    if (nblk == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_blk_mode, dim3((uint32_t)((nblk + 255) / 256)), dim3(256), 0, s, blk_file, files, mode, nblk);
     return hipGetLastError();
 }
 

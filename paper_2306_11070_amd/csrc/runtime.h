@@ -44,6 +44,7 @@ struct huff_batch {
     huff::FileDesc* d_dec = nullptr;   // [nfiles], first = first decode lane (256-aligned)
     uint32_t* d_tile_file = nullptr;
     uint32_t* d_blk_file = nullptr;    // [nitems / kDecBatchBlock] decode block -> file, or null (search)
+    uint8_t* d_blk_mode = nullptr;     // [nitems / kDecBatchBlock] 1: the block's codes pass the peek table
     uint16_t* d_tile_hist = nullptr;
     uint32_t* d_tile_local = nullptr;
     unsigned long long* d_blk_tail = nullptr;
