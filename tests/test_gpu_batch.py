@@ -289,3 +289,35 @@ def test_batch_codes_past_the_table(P, codec):
             _check_file(f, a, chunk, sub)
             assert torch.equal(f["out"], x)
         b.close()
+
+
+@pytest.mark.parametrize("kind", ["all_short", "all_long", "alternating"])
+def test_batch_decode_block_modes(P, codec, kind):
+    """The two staged decode launches split a batch's blocks by the per-block
+    mode map: batches whose files all fit the peek table, all pass it, or
+    alternate file by file (small and large files, so blocks of both modes
+    sit side by side), decoded twice (the map is rewritten at every decode)."""
+    sizes = [70_001, 3, 300_017, 16_384, 1 << 20, 65_536 + 9]
+    data = []
+    for i, n in enumerate(sizes):
+        long_codes = kind == "all_long" or (kind == "alternating" and i % 2 == 1)
+        s = 1.8 if long_codes else 1.0
+        data.append(datagen.zipf_iid(n, 60 + i, s, datagen.A256, 256 if long_codes else 64))
+    for i, a in enumerate(data):
+        if a.size > 1000:  # the 3-byte file has a short code whatever its source
+            ml = int(oracle.code_lengths(np.bincount(a, minlength=256)).max())
+            assert (ml > 10) == (kind == "all_long" or (kind == "alternating" and i % 2 == 1)), (i, ml)
+    _say(f"batch block modes {kind}")
+    xs = [dev(a) for a in data]
+    files = P.batch_buffers(codec, xs, 16384, 64)
+    b = P.Batch(codec, files, 16384, 64)
+    b.compress(graph=True)
+    for rep in range(2):
+        for f in files:
+            f["out"].zero_()
+        b.decode(graph=True)
+        torch.cuda.synchronize()
+        for f, a, x in zip(files, data, xs):
+            _check_file(f, a, 16384, 64)
+            assert torch.equal(f["out"], x), (kind, rep)
+    b.close()
